@@ -1,0 +1,133 @@
+"""Benchmark: AdvancedGreedy rounds on the 4M-vertex R-MAT graph on one MI355X.
+
+A step is one greedy round of the hot path: theta = 10,000 live-edge samples, each with
+live-edge decisions, reachability from the merged seed, the dominator tree, subtree sizes
+and the exact accumulation of the decrease counts, followed by the device-side argmax and
+block of the round's winner (Algorithms 2 and 3 of arXiv 2302.13529). Inputs are seeded
+synthetic data resident in HBM before the timed region starts.
+
+Prints one JSON line: samples/s over the timed steps, the roofline figure of the
+sampling/dominator kernel (algorithmic bytes per launch over its average launch time,
+against MI355X's 8 TB/s HBM peak), and the CPU checker timed on a bounded sample of the
+same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(stats: dict, n_seeds: int) -> float:
+    """8 B per expanded vertex (its row_ptr pair; the seeds and every reached vertex), 8 B
+    per scanned edge (target id + threshold), 8 B per reached vertex (counter update)."""
+    expanded = stats["samples"] * n_seeds + stats["reached"]
+    return 8.0 * expanded + 8.0 * stats["edges_scanned"] + 8.0 * stats["reached"]
+
+
+def traffic_from_profile(path: str):
+    """HBM bytes per launch from a committed counter summary, when one exists."""
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            for line in f:
+                if line.startswith("traffic_bytes_per_launch:"):
+                    return float(line.split(":", 1)[1])
+    except OSError:
+        return None
+    return None
+
+
+def cpu_baseline(inst, theta_sample: int) -> dict:
+    from oracle import oracle as orc
+    t0 = time.perf_counter()
+    _, st = orc.decrease(inst.n, inst.row_ptr, inst.col, inst.prob, inst.seeds, None,
+                         theta_sample, 0)
+    dt = time.perf_counter() - t0
+    return {"value": st["samples"] / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"{theta_sample} of the {inst.theta} samples of greedy round 0 "
+                      f"(no blockers, key 0) on {inst.name}, single-threaded C checker, "
+                      f"{dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-samples", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(samples would shard across GPUs with one integer reduction of the counts "
+              "per round; see the design notes)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2302_13529_amd import binding, graphgen as gg
+
+    torch.cuda.set_device(0)
+    print("[bench] generating rmat22 workload", file=sys.stderr, flush=True)
+    inst = gg.large_plain()
+    g = binding.Graph(inst.row_ptr, inst.col, inst.prob)
+    theta = inst.theta
+    print(f"[bench] warmup {args.warmup} rounds", file=sys.stderr, flush=True)
+    if args.warmup > 0:
+        g.greedy(inst.seeds, args.warmup, theta, 1000, binding.IMIN_AG)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} rounds", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    B, st = g.greedy(inst.seeds, args.steps, theta, 0, binding.IMIN_AG)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g.close()
+
+    samples = st["samples"]
+    launches = args.steps
+    alg = algorithmic_bytes(st, len(inst.seeds))
+    kernel_s = st["kernel_ms"] / 1e3
+    achieved = alg / kernel_s / 1e9
+    traffic = traffic_from_profile(os.path.join(ROOT, "profiles", "decrease_kernel_rmat22_pmc.txt"))
+    out = {
+        "metric": "live-edge samples/sec incl. dominator decrease",
+        "value": samples / dt,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": inst.name, "n": inst.n, "m": inst.m, "seeds": len(inst.seeds),
+                   "theta": theta, "step": "one AdvancedGreedy round", "parallelism": "none"},
+        "teps": st["edges_scanned"] / dt,
+        "reached_per_sample": st["reached"] / samples,
+        "blockers": [int(x) for x in B],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "decrease_kernel",
+                     "algorithmic_bytes_per_launch": alg / launches,
+                     "avg_launch_ms": st["kernel_ms"] / launches},
+    }
+    if not args.no_cpu:
+        print(f"[bench] cpu baseline on {args.cpu_samples} samples", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_samples)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

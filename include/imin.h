@@ -1,0 +1,154 @@
+/*
+ * imin.h -- C ABI of libimin: GPU estimation of the expected-spread decrease of every
+ * candidate blocker from live-edge samples, and the greedy blocker selection built on it,
+ * for influence minimisation under the independent cascade model (arXiv 2302.13529).
+ *
+ * Problem (Section III-B, "Problem Statement"): given a directed graph G = (V, E) with a
+ * propagation probability p(u,v) on every edge, a seed set S and a budget b, find a blocker
+ * set B, a subset of V \ S with |B| <= b, that minimises the expected spread
+ * E(S, G[V \ B]). A blocked vertex never becomes active (Definition 2).
+ *
+ * Conventions shared by every call:
+ *   - Vertices are 0..n-1. Edges are given in CSR form: the out-edges of u are
+ *     col[row_ptr[u] .. row_ptr[u+1]-1]; the edge id of an edge is its CSR position.
+ *   - Multiple seeds act as one merged source (Section V, "From Multiple Seeds to One
+ *     Seed"): a virtual root whose edge to v is live iff at least one seed->v edge is live.
+ *     Duplicate seeds are treated as a set. Edges into seeds are irrelevant.
+ *   - Live-edge sampling (Definition 4): in sample j of a call whose Philox key is k,
+ *     edge e is live iff  (W >> 8) < ceil(p_e * 2^24)  (p_e >= 1: always live), where
+ *     W = word (e & 3) of Philox4x32-10 applied to counter (e >> 2, j, 0, 0) with key
+ *     (low 32 bits of k, high 32 bits of k) (Salmon et al., SC'11). This is exactly the
+ *     float test U < p_e with U = (W >> 8) * 2^-24, so results are a pure function of
+ *     (graph, S, blocked set, theta, k) and independent of launch configuration.
+ *   - Counts are exact integers. counts[u] = D[u] = sum over samples j < theta of c_j[u],
+ *     where c_j[u] is the number of vertices of sample j whose every path from the merged
+ *     source passes through u; by Theorem 6 this is the size of u's subtree in the
+ *     dominator tree of the sample. The estimated decrease of Algorithm 2 is
+ *     Delta[u] = D[u] / theta (Theorem 4); D is returned undivided so ties are exact.
+ *   - Every call is synchronous. The caller owns every host array; the library copies its
+ *     inputs and keeps no caller pointer after returning. Outputs are written only when the
+ *     call returns IMIN_OK; on any error they are left untouched.
+ */
+#ifndef IMIN_H
+#define IMIN_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define IMIN_API __attribute__((visibility("default")))
+#else
+#define IMIN_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+    IMIN_OK = 0,
+    IMIN_EINVAL = -1,  /* an argument violates the contract stated at the call */
+    IMIN_ENOMEM = -2,  /* host or device memory could not be allocated */
+    IMIN_EDEVICE = -3, /* no usable GPU, or a HIP call failed */
+    IMIN_ERANGE = -4   /* a size exceeds what the library supports (e.g. m >= 2^31) */
+};
+
+/* Greedy drivers for imin_greedy. */
+enum {
+    IMIN_AG = 0, /* AdvancedGreedy, Algorithm 3 */
+    IMIN_GR = 1  /* GreedyReplace, Algorithm 4 */
+};
+
+/* Opaque handle: the device-resident graph and its per-slot scratch. */
+typedef struct imin_graph imin_graph;
+
+/* Work counters of a call (summed over every Algorithm 2 call it made). */
+typedef struct {
+    uint64_t samples;       /* live-edge samples processed (theta per Algorithm 2 call) */
+    uint64_t reached;       /* sum over samples of reached non-seed vertices |R_j| */
+    uint64_t edges_scanned; /* sum over samples of out-edges of the seeds and of R_j */
+    uint64_t live_edges;    /* sum over samples of live edges whose target is neither a
+                               seed nor blocked, leaving a seed or a vertex of R_j */
+    uint64_t spilled;       /* samples re-run in large-capacity scratch after overflow */
+    double device_ms;       /* GPU time of the whole call, measured with HIP events */
+    double kernel_ms;       /* GPU time of the sampling/dominator kernel launches alone,
+                               summed over the call (HIP events around each launch) */
+} imin_stats;
+
+/*
+ * imin_graph_create -- validate a graph and make it resident on the current HIP device.
+ *   n        number of vertices, n >= 1.
+ *   m        number of edges, 0 <= m < 2^31; must equal row_ptr[n].
+ *   row_ptr  host int32[n+1], row_ptr[0] = 0, non-decreasing.
+ *   col      host int32[m], every entry in [0, n). May be NULL when m = 0.
+ *   prob     host float[m], the propagation probability p(u,v) of each edge (Section III-A),
+ *            each in [0, 1]; NaN is rejected. Self-loops and repeated edges are allowed
+ *            (each edge is an independent coin; self-loops never matter).
+ *   out      receives the handle; release it with imin_graph_destroy.
+ * The probabilities are turned into 24-bit thresholds ceil(p * 2^24) on the host; the
+ * device never does floating-point arithmetic on them.
+ * Errors: IMIN_EINVAL for any violation above (out is then untouched), IMIN_ERANGE for
+ * m >= 2^31, IMIN_ENOMEM, IMIN_EDEVICE.
+ */
+IMIN_API int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col,
+                      const float *prob, imin_graph **out);
+
+/* Release a handle and all device memory it owns. NULL is ignored. */
+IMIN_API void imin_graph_destroy(imin_graph *g);
+
+/*
+ * imin_decrease -- Algorithm 2 (DecreaseESComputation) on G[V \ B] with exact integer sums.
+ *   S, nS    host int32[nS], the seed set; nS >= 1, each seed in [0, n).
+ *   blocked  host uint8[n] with 1 for every vertex of B (0 otherwise), or NULL for B empty.
+ *            A seed may not be blocked (B is a subset of V \ S, Definition 2).
+ *   theta    number of live-edge samples, 1 <= theta <= 2^31 (IMIN_ERANGE above).
+ *   seed     the Philox key k of this call.
+ *   counts   host uint64[n], receives D[u]; 0 for seeds, blocked and never-reached vertices.
+ *   stats    optional (may be NULL), receives the work counters.
+ * Errors: IMIN_EINVAL (bad seed, seed blocked, theta = 0, NULL g/S/counts), IMIN_ENOMEM,
+ * IMIN_EDEVICE.
+ */
+IMIN_API int imin_decrease(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *blocked,
+                  uint32_t theta, uint64_t seed, uint64_t *counts, imin_stats *stats);
+
+/*
+ * imin_greedy -- AdvancedGreedy (Algorithm 3) or GreedyReplace (Algorithm 4).
+ *   b          budget, b >= 0.
+ *   theta      samples per Algorithm 2 call, 1 <= theta <= 2^31 (IMIN_ERANGE above).
+ *   seed       call r (r = 0, 1, ...) of Algorithm 2 uses Philox key seed + r (mod 2^64),
+ *              so round r is bit-identical to imin_decrease with the blockers chosen before
+ *              it and key seed + r.
+ *   mode       IMIN_AG or IMIN_GR.
+ *   blockers   host int32[b], receives the blocker slots in insertion order.
+ *   n_blockers receives the number of blockers written.
+ *   stats      optional, summed over all Algorithm 2 calls.
+ * Argmax ties go to the smallest vertex id; seeds are never candidates.
+ *   AG: min(b, n - |S|) rounds; round r blocks argmax of D over V \ (S u B).
+ *   GR: CB = out-neighbours of the seeds that are not seeds; min(|CB|, b) rounds pick the
+ *       argmax over the remaining CB; then, for each chosen blocker u in reverse insertion
+ *       order (over a snapshot of that order), u is unblocked, D is re-estimated, the argmax
+ *       x over V \ (S u B) takes u's slot, and the pass stops at the first x == u.
+ * Errors: IMIN_EINVAL (as imin_decrease, b < 0, unknown mode, NULL outputs), IMIN_ENOMEM,
+ * IMIN_EDEVICE.
+ */
+IMIN_API int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t theta,
+                uint64_t seed, int mode, int32_t *blockers, int32_t *n_blockers,
+                imin_stats *stats);
+
+/*
+ * imin_set_launch -- override the launch shape used for later calls on g (0 keeps the
+ * automatic choice for that field). slots: concurrent samples, one workgroup each.
+ * extra_cap: per-slot capacity for non-tree live edges; samples that exceed it are re-run
+ * in large-capacity scratch. Results never depend on these values; they exist so tests can
+ * check that, and to tune. Errors: IMIN_EINVAL for negative values or NULL g.
+ */
+IMIN_API int imin_set_launch(imin_graph *g, int32_t slots, int64_t extra_cap);
+
+/* Human-readable text of a status code (static storage). */
+IMIN_API const char *imin_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IMIN_H */

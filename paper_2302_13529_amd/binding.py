@@ -1,0 +1,164 @@
+"""ctypes binding of libimin (include/imin.h): argument marshalling only.
+
+The functions keep the C names (``imin_graph_create``, ``imin_decrease``, ``imin_greedy``,
+``imin_set_launch``, ``imin_graph_destroy``, ``imin_strerror``); ``Graph`` wraps them for
+convenience. Every step of the estimate runs in the library's HIP kernels; if the library
+is missing this module raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libimin.so")
+
+IMIN_OK, IMIN_EINVAL, IMIN_ENOMEM, IMIN_EDEVICE, IMIN_ERANGE = 0, -1, -2, -3, -4
+IMIN_AG, IMIN_GR = 0, 1
+
+
+class IminError(RuntimeError):
+    def __init__(self, func: str, status: int):
+        super().__init__(f"{func} failed: {status} ({imin_strerror(status)})")
+        self.status = status
+
+
+class imin_stats(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_uint64), ("reached", ctypes.c_uint64),
+                ("edges_scanned", ctypes.c_uint64), ("live_edges", ctypes.c_uint64),
+                ("spilled", ctypes.c_uint64), ("device_ms", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libimin.so (built by ``paper_2302_13529_amd.build``); raise if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch ships its own HIP runtime; importing it first makes libimin bind to that same
+    # runtime instead of loading a second copy into the process.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2302_13529_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.imin_graph_create.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P,
+                                      ctypes.POINTER(ctypes.c_void_p)]
+    lib.imin_graph_create.restype = ctypes.c_int
+    lib.imin_graph_destroy.argtypes = [P]
+    lib.imin_graph_destroy.restype = None
+    lib.imin_decrease.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_uint32, ctypes.c_uint64, P,
+                                  ctypes.POINTER(imin_stats)]
+    lib.imin_decrease.restype = ctypes.c_int
+    lib.imin_greedy.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
+                                ctypes.c_uint64, ctypes.c_int, P, P, ctypes.POINTER(imin_stats)]
+    lib.imin_greedy.restype = ctypes.c_int
+    lib.imin_set_launch.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
+    lib.imin_set_launch.restype = ctypes.c_int
+    lib.imin_strerror.argtypes = [ctypes.c_int]
+    lib.imin_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def imin_strerror(status: int) -> str:
+    return load().imin_strerror(status).decode()
+
+
+def imin_graph_create(n: int, row_ptr, col, prob) -> int:
+    """Returns the opaque handle (an integer address)."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    prob = np.ascontiguousarray(prob, dtype=np.float32)
+    h = ctypes.c_void_p()
+    rc = load().imin_graph_create(int(n), int(col.shape[0]), _p(row_ptr), _p(col), _p(prob),
+                                  ctypes.byref(h))
+    if rc != IMIN_OK:
+        raise IminError("imin_graph_create", rc)
+    return h.value
+
+
+def imin_graph_destroy(handle: int) -> None:
+    load().imin_graph_destroy(ctypes.c_void_p(handle))
+
+
+def imin_set_launch(handle: int, slots: int = 0, extra_cap: int = 0) -> None:
+    rc = load().imin_set_launch(ctypes.c_void_p(handle), int(slots), int(extra_cap))
+    if rc != IMIN_OK:
+        raise IminError("imin_set_launch", rc)
+
+
+def imin_decrease(handle: int, n: int, seeds, blocked, theta: int, seed: int):
+    """Exact counts D (uint64[n]) and the stats dict of one Algorithm 2 call."""
+    S = np.ascontiguousarray(seeds, dtype=np.int32)
+    blk = None if blocked is None else np.ascontiguousarray(blocked, dtype=np.uint8)
+    if blk is not None and blk.shape[0] != n:
+        raise ValueError("blocked must have n entries")
+    D = np.zeros(n, dtype=np.uint64)
+    st = imin_stats()
+    rc = load().imin_decrease(ctypes.c_void_p(handle), _p(S), S.shape[0], _p(blk), int(theta),
+                              int(seed) & (2**64 - 1), _p(D), ctypes.byref(st))
+    if rc != IMIN_OK:
+        raise IminError("imin_decrease", rc)
+    return D, st.as_dict()
+
+
+def imin_greedy(handle: int, seeds, b: int, theta: int, seed: int, mode: int):
+    """Blocker slots (int32) and the summed stats of AG (mode 0) or GR (mode 1)."""
+    S = np.ascontiguousarray(seeds, dtype=np.int32)
+    out = np.zeros(max(int(b), 1), dtype=np.int32)
+    nb = np.zeros(1, dtype=np.int32)
+    st = imin_stats()
+    rc = load().imin_greedy(ctypes.c_void_p(handle), _p(S), S.shape[0], int(b), int(theta),
+                            int(seed) & (2**64 - 1), int(mode), _p(out), _p(nb),
+                            ctypes.byref(st))
+    if rc != IMIN_OK:
+        raise IminError("imin_greedy", rc)
+    return out[: nb[0]].copy(), st.as_dict()
+
+
+class Graph:
+    """A device-resident graph (one ``imin_graph`` handle)."""
+
+    def __init__(self, row_ptr, col, prob):
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        self.n = int(row_ptr.shape[0] - 1)
+        self.handle = imin_graph_create(self.n, row_ptr, col, prob)
+
+    def decrease(self, seeds, blocked=None, theta: int = 1000, seed: int = 0):
+        return imin_decrease(self.handle, self.n, seeds, blocked, theta, seed)
+
+    def greedy(self, seeds, b: int, theta: int, seed: int = 0, mode: int = IMIN_AG):
+        return imin_greedy(self.handle, seeds, b, theta, seed, mode)
+
+    def set_launch(self, slots: int = 0, extra_cap: int = 0) -> None:
+        imin_set_launch(self.handle, slots, extra_cap)
+
+    def close(self) -> None:
+        if self.handle:
+            imin_graph_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,75 @@
+// imin_internal.h -- shapes shared by the host API and the HIP kernels of libimin.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace imin {
+
+constexpr int kBlock = 256;  // threads per workgroup; one workgroup works on one sample at a time
+
+// Per slot and vertex: the epoch of the sample that last reached the vertex, and its
+// local id in that sample. Both halves live in one 8-byte entry so a lookup touches one line.
+struct SlotEntry {
+    uint32_t stamp;
+    int32_t lid;
+};
+
+// Scratch of `slots` concurrent samples. Arrays are slot-major: slot s owns
+// [s * n, (s + 1) * n) of `map`, [s * lcap, (s + 1) * lcap) of the local arrays, and so on.
+struct Workspace {
+    int32_t slots = 0;
+    int64_t lcap = 0;        // local vertices per sample (root included)
+    int64_t xcap = 0;        // non-tree live edges per sample
+    SlotEntry *map = nullptr;  // slots * n
+    int32_t *glob = nullptr;   // slots * lcap: local id -> vertex id
+    int32_t *par0 = nullptr;   // slots * lcap: parent in the BFS spanning tree
+    int32_t *tdom = nullptr;   // slots * lcap: tentative immediate dominator
+    int32_t *tnew = nullptr;   // slots * lcap: next value of tdom (Jacobi step)
+    int32_t *csz = nullptr;    // slots * lcap: dominator-subtree sizes
+    int32_t *lvl = nullptr;    // slots * (lcap + 1): first local id of each BFS level
+    int2 *extra = nullptr;     // slots * xcap: (source local id, target vertex -> local id)
+    uint32_t *epoch = nullptr; // slots
+    uint64_t epochs_used = 0;  // host-side bound on the largest epoch issued so far
+    size_t bytes = 0;
+};
+
+// Everything one launch of the decrease kernel reads or writes.
+struct DecreaseArgs {
+    const int32_t *row_ptr;  // n + 1
+    const uint4 *edges;      // ceil(m / 4) * 2 uint4: (col, thr) pairs, 4 edges = 32 bytes
+    const uint32_t *inelig;  // bitmap over vertices: seed or blocked
+    const int32_t *seeds;    // distinct seeds
+    int32_t nseeds;
+    int32_t n;
+    uint32_t key_lo, key_hi; // Philox key of the call
+    uint32_t theta;          // samples 0..theta-1 when sample_list is null
+    const uint32_t *sample_list;   // else: samples sample_list[0..*sample_count)
+    const uint32_t *sample_count;
+    uint32_t *next;          // work counter of this launch
+    unsigned long long *D;   // n decrease counters
+    unsigned long long *stats; // samples, reached, edges scanned, live edges
+    uint32_t *ovf_list;      // samples whose scratch overflowed (when spill_ok)
+    uint32_t *ovf_count;
+    uint32_t *error;         // set when a sample overflows with spill_ok == 0
+    int32_t spill_ok;
+    Workspace ws;
+};
+
+// decrease.hip
+hipError_t launch_decrease(const DecreaseArgs &a, hipStream_t stream);
+
+// select.hip
+hipError_t launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long value,
+                           hipStream_t stream);
+hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t stream);
+// Argmax of D over candidates (mode 0: bit of `bits` clear; mode 1: bit of `bits` set),
+// ties to the smallest id. Then: set the winner's bit in `inelig`, clear it in `cand`
+// (if non-null), store it in B[slot] and *out_x. *out_x = -1 when there is no candidate.
+hipError_t launch_argmax_apply(const unsigned long long *D, const uint32_t *bits, int mode,
+                               int32_t n, unsigned long long *part_d, int32_t *part_i,
+                               int32_t parts, uint32_t *inelig, uint32_t *cand, int32_t *B,
+                               int32_t slot, int32_t *out_x, hipStream_t stream);
+hipError_t launch_set_bit(uint32_t *bits, int32_t v, int value, hipStream_t stream);
+
+}  // namespace imin

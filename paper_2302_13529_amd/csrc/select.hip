@@ -1,0 +1,147 @@
+// select.hip -- device-side round selection of the greedy drivers (Algorithm 3, lines
+// choosing x = argmax Delta; Algorithm 4, the same over CB or over V \ B), plus fills.
+// Ties go to the smallest vertex id, which makes the argmax order-independent.
+#include "imin_internal.h"
+
+namespace imin {
+namespace {
+
+constexpr int kSelBlock = 256;
+
+__global__ void fill_u64_kernel(unsigned long long *p, int64_t count, unsigned long long value)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t count, uint32_t value)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// (d, i) beats (bd, bi) when d is larger, or equal with a smaller id; i = -1 is "none".
+__device__ __forceinline__ void better(unsigned long long &bd, int &bi, unsigned long long d, int i)
+{
+    if (i < 0) return;
+    if (bi < 0 || d > bd || (d == bd && i < bi)) {
+        bd = d;
+        bi = i;
+    }
+}
+
+__device__ void block_best(unsigned long long &bd, int &bi)
+{
+    __shared__ unsigned long long sd[kSelBlock];
+    __shared__ int si[kSelBlock];
+    sd[threadIdx.x] = bd;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s = kSelBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            unsigned long long d = sd[threadIdx.x];
+            int i = si[threadIdx.x];
+            better(d, i, sd[threadIdx.x + s], si[threadIdx.x + s]);
+            sd[threadIdx.x] = d;
+            si[threadIdx.x] = i;
+        }
+        __syncthreads();
+    }
+    bd = sd[0];
+    bi = si[0];
+}
+
+__global__ void argmax_partial_kernel(const unsigned long long *D, const uint32_t *bits, int mode,
+                                      int32_t n, unsigned long long *part_d, int32_t *part_i)
+{
+    unsigned long long bd = 0;
+    int bi = -1;
+    for (int64_t v = blockIdx.x * (int64_t)kSelBlock + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kSelBlock) {
+        const bool bit = (bits[v >> 5] >> (v & 31)) & 1u;
+        const bool cand = mode == 0 ? !bit : bit;
+        if (cand) better(bd, bi, D[v], (int)v);
+    }
+    block_best(bd, bi);
+    if (threadIdx.x == 0) {
+        part_d[blockIdx.x] = bd;
+        part_i[blockIdx.x] = bi;
+    }
+}
+
+__global__ void argmax_final_kernel(const unsigned long long *part_d, const int32_t *part_i,
+                                    int32_t parts, uint32_t *inelig, uint32_t *cand, int32_t *B,
+                                    int32_t slot, int32_t *out_x)
+{
+    unsigned long long bd = 0;
+    int bi = -1;
+    for (int p = threadIdx.x; p < parts; p += kSelBlock) better(bd, bi, part_d[p], part_i[p]);
+    block_best(bd, bi);
+    if (threadIdx.x == 0) {
+        if (bi >= 0) {
+            inelig[bi >> 5] |= 1u << (bi & 31);
+            if (cand) cand[bi >> 5] &= ~(1u << (bi & 31));
+            B[slot] = bi;
+        }
+        *out_x = bi;
+    }
+}
+
+__global__ void set_bit_kernel(uint32_t *bits, int32_t v, int value)
+{
+    if (value) bits[v >> 5] |= 1u << (v & 31);
+    else bits[v >> 5] &= ~(1u << (v & 31));
+}
+
+int grid_for(int64_t count)
+{
+    int64_t g = (count + kSelBlock - 1) / kSelBlock;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long value,
+                           hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(count)), dim3(kSelBlock), 0, stream, p,
+                       count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(count)), dim3(kSelBlock), 0, stream, p,
+                       count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_argmax_apply(const unsigned long long *D, const uint32_t *bits, int mode,
+                               int32_t n, unsigned long long *part_d, int32_t *part_i,
+                               int32_t parts, uint32_t *inelig, uint32_t *cand, int32_t *B,
+                               int32_t slot, int32_t *out_x, hipStream_t stream)
+{
+    int g = grid_for(n);
+    if (g > parts) g = parts;
+    hipLaunchKernelGGL(argmax_partial_kernel, dim3(g), dim3(kSelBlock), 0, stream, D, bits, mode,
+                       n, part_d, part_i);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(argmax_final_kernel, dim3(1), dim3(kSelBlock), 0, stream, part_d, part_i, g,
+                       inelig, cand, B, slot, out_x);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_bit(uint32_t *bits, int32_t v, int value, hipStream_t stream)
+{
+    hipLaunchKernelGGL(set_bit_kernel, dim3(1), dim3(1), 0, stream, bits, v, value);
+    return hipGetLastError();
+}
+
+}  // namespace imin

@@ -75,42 +75,44 @@ def chung_lu_edges(n: int, m_target: int, gamma: float, rng: np.random.Generator
 
 def _rmat_draw(scale: int, count: int, abcd, rng: np.random.Generator):
     a, b, c, _ = abcd
-    src = np.zeros(count, dtype=np.int64)
-    dst = np.zeros(count, dtype=np.int64)
+    src = np.zeros(count, dtype=np.int32)
+    dst = np.zeros(count, dtype=np.int32)
+    r = np.empty(count, dtype=np.float32)
     for _level in range(scale):
-        r = rng.random(count, dtype=np.float32)
-        sbit = r >= (a + b)
-        dbit = ((r >= a) & (r < a + b)) | (r >= a + b + c)
-        src = (src << 1) | sbit
-        dst = (dst << 1) | dbit
+        rng.random(count, dtype=np.float32, out=r)
+        sbit = r >= np.float32(a + b)
+        dbit = ((r >= np.float32(a)) & (r < np.float32(a + b))) | (r >= np.float32(a + b + c))
+        src <<= 1
+        src |= sbit
+        dst <<= 1
+        dst |= dbit
     return src, dst
 
 
 def rmat_edges(scale: int, m_unique: int, rng: np.random.Generator,
                abcd=(0.57, 0.19, 0.19, 0.05)):
-    """R-MAT edges drawn until m_unique distinct non-loop pairs exist, then relabelled."""
+    """R-MAT edges: distinct non-loop pairs drawn until m_unique exist (a uniform subset of
+    them is kept if a batch overshoots), then relabelled by a random permutation."""
     n = 1 << scale
-    src = np.zeros(0, dtype=np.int64)
-    dst = np.zeros(0, dtype=np.int64)
-    want = m_unique
-    while True:
-        s2, d2 = _rmat_draw(scale, int(want * 1.15) + 1024, abcd, rng)
-        src = np.concatenate([src, s2])
-        dst = np.concatenate([dst, d2])
-        src, dst = _dedup_in_draw_order(src, dst, n, None)
-        if src.shape[0] >= m_unique:
-            src, dst = src[:m_unique], dst[:m_unique]
-            break
-        want = m_unique - src.shape[0]
-    perm = rng.permutation(n).astype(np.int64)
-    return perm[src].astype(np.int32), perm[dst].astype(np.int32)
+    keys = np.zeros(0, dtype=np.int64)
+    while keys.size < m_unique:
+        need = m_unique - keys.size
+        s, d = _rmat_draw(scale, int(need * 1.2) + 1024, abcd, rng)
+        k = (s.astype(np.int64) << scale) | d
+        keys = np.unique(np.concatenate([keys, k[s != d]]))
+    if keys.size > m_unique:
+        keep = np.sort(rng.choice(keys.size, m_unique, replace=False))
+        keys = keys[keep]
+    perm = rng.permutation(n).astype(np.int32)
+    return perm[keys >> scale], perm[keys & (n - 1)]
 
 
 def to_csr(n: int, src: np.ndarray, dst: np.ndarray):
     """CSR with rows sorted by target id; returns (row_ptr int32[n+1], col int32[m])."""
-    order = np.lexsort((dst, src))
-    col = dst[order].astype(np.int32)
-    counts = np.bincount(src, minlength=n)
+    key = src.astype(np.int64) * n + dst.astype(np.int64)
+    key.sort()
+    col = (key % n).astype(np.int32)
+    counts = np.bincount((key // n).astype(np.int64), minlength=n)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
     assert row_ptr[-1] < 2**31

@@ -1,0 +1,79 @@
+"""The C-ABI library loads on the CPU, exports every symbol include/imin.h declares, and
+rejects invalid graphs before touching a device (host logic only; no compute calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2302_13529_amd import binding
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "include", "imin.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return re.findall(r"IMIN_API\s+[\w\s\*]+?\b(imin_\w+)\s*\(", text)
+
+
+def test_header_declares_the_api():
+    names = set(declared_functions())
+    assert {"imin_graph_create", "imin_graph_destroy", "imin_decrease", "imin_greedy",
+            "imin_set_launch", "imin_strerror"} <= names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror():
+    assert binding.imin_strerror(binding.IMIN_OK) == "ok"
+    assert binding.imin_strerror(binding.IMIN_EINVAL) == "invalid argument"
+    assert binding.imin_strerror(12345) == "unknown status"
+
+
+@pytest.mark.parametrize("case", ["rowptr0", "nonmono", "colrange", "nan", "pneg", "pbig",
+                                  "mmismatch", "n0"])
+def test_graph_create_rejects_invalid(case):
+    n = 4
+    row_ptr = np.array([0, 1, 2, 3, 3], np.int32)
+    col = np.array([1, 2, 3], np.int32)
+    prob = np.array([0.5, 0.5, 0.5], np.float32)
+    m = 3
+    if case == "rowptr0":
+        row_ptr = np.array([1, 1, 2, 3, 3], np.int32)
+    elif case == "nonmono":
+        row_ptr = np.array([0, 2, 1, 3, 3], np.int32)
+    elif case == "colrange":
+        col = np.array([1, 2, 4], np.int32)
+    elif case == "nan":
+        prob = np.array([0.5, np.nan, 0.5], np.float32)
+    elif case == "pneg":
+        prob = np.array([0.5, -0.1, 0.5], np.float32)
+    elif case == "pbig":
+        prob = np.array([0.5, 1.5, 0.5], np.float32)
+    elif case == "mmismatch":
+        m = 2
+    elif case == "n0":
+        n = 0
+    lib = binding.load()
+    h = ctypes.c_void_p()
+    rc = lib.imin_graph_create(n, m, row_ptr.ctypes.data_as(ctypes.c_void_p),
+                               col.ctypes.data_as(ctypes.c_void_p),
+                               prob.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
+    assert rc == binding.IMIN_EINVAL
+    assert h.value is None
+
+
+def test_null_handle_is_rejected():
+    lib = binding.load()
+    D = np.zeros(4, np.uint64)
+    S = np.array([0], np.int32)
+    assert lib.imin_decrease(None, S.ctypes.data_as(ctypes.c_void_p), 1, None, 10, 0,
+                             D.ctypes.data_as(ctypes.c_void_p), None) == binding.IMIN_EINVAL
+    assert lib.imin_set_launch(None, 1, 1) == binding.IMIN_EINVAL
+    lib.imin_graph_destroy(None)
