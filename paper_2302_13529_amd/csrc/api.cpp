@@ -40,6 +40,9 @@ struct imin_graph {
     int32_t B_cap = 0;
     int32_t *d_x = nullptr;
     Workspace main_ws, big_ws;
+    std::vector<int32_t> marked;   // vertices stamped kInelig in every slot map
+    bool marks_valid = true;       // false after a call that stopped half-way
+    int32_t *d_list = nullptr;     // n: vertex lists for stamping
     std::vector<hipEvent_t> kev;  // pairs around each decrease launch of the current call
     size_t kev_used = 0;
     int32_t force_slots = 0;
@@ -72,11 +75,7 @@ void dfree(T *&p)
 void free_ws(Workspace &ws)
 {
     dfree(ws.map);
-    dfree(ws.glob);
-    dfree(ws.par0);
-    dfree(ws.tdom);
-    dfree(ws.tnew);
-    dfree(ws.csz);
+    dfree(ws.loc);
     dfree(ws.lvl);
     dfree(ws.extra);
     dfree(ws.epoch);
@@ -85,7 +84,7 @@ void free_ws(Workspace &ws)
 
 size_t slot_bytes(int64_t n, int64_t lcap, int64_t xcap)
 {
-    return (size_t)n * sizeof(imin::SlotEntry) + (size_t)lcap * 5 * sizeof(int32_t) +
+    return (size_t)n * sizeof(imin::SlotEntry) + (size_t)lcap * sizeof(imin::LocalVtx) +
            (size_t)(lcap + 1) * sizeof(int32_t) + (size_t)xcap * sizeof(int2) + sizeof(uint32_t);
 }
 
@@ -95,11 +94,7 @@ int alloc_ws(imin_graph *g, Workspace &ws, int32_t slots, int64_t lcap, int64_t 
     free_ws(ws);
     const size_t S = (size_t)slots;
     bool good = ok(hipMalloc(&ws.map, S * (size_t)g->n * sizeof(imin::SlotEntry))) &&
-                ok(hipMalloc(&ws.glob, S * (size_t)lcap * sizeof(int32_t))) &&
-                ok(hipMalloc(&ws.par0, S * (size_t)lcap * sizeof(int32_t))) &&
-                ok(hipMalloc(&ws.tdom, S * (size_t)lcap * sizeof(int32_t))) &&
-                ok(hipMalloc(&ws.tnew, S * (size_t)lcap * sizeof(int32_t))) &&
-                ok(hipMalloc(&ws.csz, S * (size_t)lcap * sizeof(int32_t))) &&
+                ok(hipMalloc(&ws.loc, S * (size_t)lcap * sizeof(imin::LocalVtx))) &&
                 ok(hipMalloc(&ws.lvl, S * (size_t)(lcap + 1) * sizeof(int32_t))) &&
                 ok(hipMalloc(&ws.extra, S * (size_t)std::max<int64_t>(xcap, 1) * sizeof(int2))) &&
                 ok(hipMalloc(&ws.epoch, S * sizeof(uint32_t)));
@@ -126,6 +121,12 @@ int alloc_ws(imin_graph *g, Workspace &ws, int32_t slots, int64_t lcap, int64_t 
 // graph whose m is below that can never overflow and needs no spill path.
 int prepare_workspaces(imin_graph *g)
 {
+    if (!g->marks_valid) {
+        free_ws(g->main_ws);
+        free_ws(g->big_ws);
+        g->marked.clear();
+        g->marks_valid = true;
+    }
     const int64_t lcap = (int64_t)g->n + 1;
     const int64_t xmax = (int64_t)g->m + 1;
     int64_t xcap = g->force_xcap > 0 ? g->force_xcap
@@ -165,7 +166,8 @@ int guard_epochs(imin_graph *g, Workspace &ws, uint32_t theta)
     }
     if (!ok(hipMemsetAsync(ws.map, 0, (size_t)ws.slots * g->n * sizeof(imin::SlotEntry),
                            g->stream)) ||
-        !ok(hipMemsetAsync(ws.epoch, 0, (size_t)ws.slots * sizeof(uint32_t), g->stream)))
+        !ok(hipMemsetAsync(ws.epoch, 0, (size_t)ws.slots * sizeof(uint32_t), g->stream)) ||
+        !ok(imin::launch_mark_bitmap(ws.map, ws.slots, g->n, g->d_inelig, g->stream)))
         return IMIN_EDEVICE;
     ws.epochs_used = theta;
     return IMIN_OK;
@@ -225,6 +227,35 @@ int upload_call_state(imin_graph *g, const std::vector<int32_t> &seeds,
     if (!ok(imin::launch_fill_u64(g->d_stats, 5, 0, g->stream)) ||
         !ok(imin::launch_fill_u32(g->d_ctrl, 4, 0, g->stream)))
         return IMIN_EDEVICE;
+    // Slot-map stamps: clear the previous call's seeds and blockers, stamp the new ones.
+    Workspace *wss[2] = {&g->main_ws, &g->big_ws};
+    g->marks_valid = false;
+    for (Workspace *ws : wss) {
+        if (ws->slots == 0) continue;
+        if (!g->marked.empty()) {
+            if (!ok(hipMemcpyAsync(g->d_list, g->marked.data(), g->marked.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, g->stream)) ||
+                !ok(imin::launch_set_stamps(ws->map, ws->slots, g->n, g->d_list,
+                                            (int32_t)g->marked.size(), 0u, g->stream)))
+                return IMIN_EDEVICE;
+        }
+        if (!ok(imin::launch_mark_bitmap(ws->map, ws->slots, g->n, g->d_inelig, g->stream)))
+            return IMIN_EDEVICE;
+    }
+    g->marked.clear();
+    for (int32_t v = 0; v < g->n; ++v)
+        if ((inelig[v >> 5] >> (v & 31)) & 1u) g->marked.push_back(v);
+    return IMIN_OK;
+}
+
+// A vertex joins (value kInelig) or leaves (value 0) the seed/blocked stamps of all slots;
+// v_dev, when non-null, holds the vertex id on the device.
+int stamp_vertex(imin_graph *g, int32_t v, const int32_t *v_dev, uint32_t value)
+{
+    Workspace *wss[2] = {&g->main_ws, &g->big_ws};
+    for (Workspace *ws : wss)
+        if (!ok(imin::launch_set_stamp(ws->map, ws->slots, g->n, v, v_dev, value, g->stream)))
+            return IMIN_EDEVICE;
     return IMIN_OK;
 }
 
@@ -259,7 +290,6 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key)
     std::memset(&a, 0, sizeof(a));
     a.row_ptr = g->d_row_ptr;
     a.edges = g->d_edges;
-    a.inelig = g->d_inelig;
     a.seeds = g->d_seeds;
     a.nseeds = nseeds;
     a.n = g->n;
@@ -344,6 +374,7 @@ void destroy(imin_graph *g)
     dfree(g->d_inelig);
     dfree(g->d_cand);
     dfree(g->d_seeds);
+    dfree(g->d_list);
     dfree(g->d_D);
     dfree(g->d_stats);
     dfree(g->d_ctrl);
@@ -433,6 +464,7 @@ int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
         ok(hipMalloc(&g->d_inelig, (size_t)g->words * sizeof(uint32_t))) &&
         ok(hipMalloc(&g->d_cand, (size_t)g->words * sizeof(uint32_t))) &&
         ok(hipMalloc(&g->d_seeds, (size_t)n * sizeof(int32_t))) &&
+        ok(hipMalloc(&g->d_list, (size_t)n * sizeof(int32_t))) &&
         ok(hipMalloc(&g->d_D, (size_t)n * sizeof(unsigned long long))) &&
         ok(hipMalloc(&g->d_stats, 5 * sizeof(unsigned long long))) &&
         ok(hipMalloc(&g->d_ctrl, 4 * sizeof(uint32_t))) &&
@@ -499,6 +531,7 @@ int imin_decrease(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *bl
     imin_stats st;
     rc = finish_call(g, &st);
     if (rc) return rc;
+    g->marks_valid = true;
     std::memcpy(counts, D.data(), (size_t)g->n * sizeof(uint64_t));
     if (stats) *stats = st;
     return IMIN_OK;
@@ -539,6 +572,8 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
                                               g->d_part_i, g->parts, g->d_inelig, nullptr,
                                               g->d_B, r, g->d_x, g->stream)))
                 return IMIN_EDEVICE;
+            rc = stamp_vertex(g, 0, g->d_x, imin::kInelig);
+            if (rc) return rc;
         }
         B.assign((size_t)rounds, -1);
         if (rounds > 0 &&
@@ -571,6 +606,8 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
                                               g->d_part_i, g->parts, g->d_inelig, g->d_cand,
                                               g->d_B, r, g->d_x, g->stream)))
                 return IMIN_EDEVICE;
+            rc = stamp_vertex(g, 0, g->d_x, imin::kInelig);
+            if (rc) return rc;
         }
         B.assign((size_t)k, -1);
         if (k > 0) {
@@ -587,6 +624,8 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
             const int32_t slot =
                 (int32_t)(std::find(B.begin(), B.end(), u) - B.begin());
             if (!ok(imin::launch_set_bit(g->d_inelig, u, 0, g->stream))) return IMIN_EDEVICE;
+            rc = stamp_vertex(g, u, nullptr, 0u);
+            if (rc) return rc;
             rc = decrease_round(g, ns, theta, seed + call);
             if (rc) return rc;
             ++call;
@@ -594,6 +633,8 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
                                               g->d_part_i, g->parts, g->d_inelig, nullptr,
                                               g->d_B, slot, g->d_x, g->stream)))
                 return IMIN_EDEVICE;
+            rc = stamp_vertex(g, 0, g->d_x, imin::kInelig);
+            if (rc) return rc;
             int32_t x = -1;
             if (!ok(hipMemcpyAsync(&x, g->d_x, sizeof(int32_t), hipMemcpyDeviceToHost,
                                    g->stream)) ||
@@ -609,6 +650,9 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
     if (rc) return rc;
     for (int32_t v : B)
         if (v < 0) return IMIN_EDEVICE;
+    // the stamped set is now the seeds plus the final blockers
+    for (int32_t v : B) g->marked.push_back(v);
+    g->marks_valid = true;
     std::copy(B.begin(), B.end(), blockers);
     *n_blockers = (int32_t)B.size();
     if (stats) *stats = st;

@@ -55,11 +55,6 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     r3 = x3;
 }
 
-__device__ __forceinline__ bool bit_set(const uint32_t *bits, int v)
-{
-    return (bits[v >> 5] >> (v & 31)) & 1u;
-}
-
 // Exclusive prefix sum over the workgroup; *total receives the sum of all values.
 __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *total)
 {
@@ -87,12 +82,12 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *tot
 
 struct SlotView {
     SlotEntry *map;
-    int32_t *glob, *par0, *tdom, *tnew, *csz, *lvl;
+    LocalVtx *loc;
+    int32_t *lvl;
     int2 *extra;
 };
 
 struct Shared {
-    int src[kBlock];
     int e0[kBlock];
     int e1[kBlock];
     int qpre[kBlock + 1];
@@ -102,21 +97,30 @@ struct Shared {
     int nextra;
     int ovf;
     int changed;
+    unsigned scanned;
+    unsigned live;
 };
 
-__device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv, Shared &sh,
+// Live edge src -> w. Returns false when w is a seed or blocked (stamp kInelig); otherwise
+// w is claimed for this sample if it was not yet reached, or the edge is kept as an extra
+// edge (edges from the merged seed never matter for dominators: their targets are its
+// children).
+__device__ __forceinline__ bool visit(const DecreaseArgs &a, const SlotView &sv, Shared &sh,
                                       int w, int src, uint32_t epoch)
 {
-    const uint32_t old = __hip_atomic_exchange(&sv.map[w].stamp, epoch, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    const uint32_t old = __hip_atomic_fetch_max(&sv.map[w].stamp, epoch, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (old == kInelig) return false;
     if (old != epoch) {
         const int id = atomicAdd(&sh.tail, 1);
         if (id < a.ws.lcap) {
             sv.map[w].lid = id;
-            sv.glob[id] = w;
-            sv.par0[id] = src;
-            sv.tdom[id] = src;
-            sv.csz[id] = 1;
+            LocalVtx rec;
+            rec.glob = w;
+            rec.par0 = src;
+            rec.tdom = src;
+            rec.csz = 1;
+            sv.loc[id] = rec;
         } else {
             sh.ovf = 1;
         }
@@ -125,25 +129,67 @@ __device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv,
         if (x < a.ws.xcap) sv.extra[x] = make_int2(src, w);
         else sh.ovf = 1;
     }
+    return true;
+}
+
+// Quad q of the current chunk: the frontier entry it belongs to and its edge quad index.
+__device__ __forceinline__ void locate(const Shared &sh, int cnt, int q, int &l, int &quad)
+{
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sh.qpre[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    l = lo;
+    quad = (sh.e0[lo] >> 2) + (q - sh.qpre[lo]);
+}
+
+// Live-edge bits of one quad for sample j: bit i set when edge 4*quad+i lies in [e0, e1)
+// and its coin falls under its threshold.
+__device__ __forceinline__ uint32_t quad_mask(const DecreaseArgs &a, int quad, uint32_t j, int e0,
+                                              int e1, uint4 p01, uint4 p23)
+{
+    uint32_t w0, w1, w2, w3;
+    philox4x32_10((uint32_t)quad, j, a.key_lo, a.key_hi, w0, w1, w2, w3);
+    const int eb = quad * 4;
+    uint32_t mask = 0;
+    mask |= (eb + 0 >= e0 && eb + 0 < e1 && (w0 >> 8) < p01.y) ? 1u : 0u;
+    mask |= (eb + 1 >= e0 && eb + 1 < e1 && (w1 >> 8) < p01.w) ? 2u : 0u;
+    mask |= (eb + 2 >= e0 && eb + 2 < e1 && (w2 >> 8) < p23.y) ? 4u : 0u;
+    mask |= (eb + 3 >= e0 && eb + 3 < e1 && (w3 >> 8) < p23.w) ? 8u : 0u;
+    return mask;
+}
+
+__device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView &sv, Shared &sh,
+                                           uint32_t mask, uint4 p01, uint4 p23, int src,
+                                           uint32_t epoch, uint32_t &live)
+{
+    while (mask) {
+        const int i = __builtin_ctz(mask);
+        mask &= mask - 1;
+        const uint32_t c = i == 0 ? p01.x : i == 1 ? p01.z : i == 2 ? p23.x : p23.z;
+        if (visit(a, sv, sh, (int)c, src, epoch)) ++live;
+    }
 }
 
 // Expand the frontier [lo, hi): seeds (from_seeds, source = merged root 0) or local ids.
+// The frontier goes in chunks of kBlock entries; the edge quads of a chunk are spread
+// evenly over the workgroup, two independent quads in flight per thread.
 __device__ void expand(const DecreaseArgs &a, const SlotView &sv, Shared &sh, bool from_seeds,
-                       int lo, int hi, uint32_t j, uint32_t epoch, unsigned long long &scanned,
-                       unsigned long long &live)
+                       int lo, int hi, uint32_t j, uint32_t epoch, uint32_t &scanned,
+                       uint32_t &live)
 {
     const int tid = threadIdx.x;
     for (int base = lo; base < hi; base += kBlock) {
         const int k = base + tid;
         int nq = 0;
         if (k < hi) {
-            const int v = from_seeds ? a.seeds[k] : sv.glob[k];
-            const int src = from_seeds ? 0 : k;
+            const int v = from_seeds ? a.seeds[k] : sv.loc[k].glob;
             const int e0 = a.row_ptr[v];
             const int e1 = a.row_ptr[v + 1];
-            scanned += (unsigned long long)(e1 - e0);
+            scanned += (uint32_t)(e1 - e0);
             nq = (e1 > e0) ? (((e1 - 1) >> 2) - (e0 >> 2) + 1) : 0;
-            sh.src[tid] = src;
             sh.e0[tid] = e0;
             sh.e1[tid] = e1;
         }
@@ -152,65 +198,55 @@ __device__ void expand(const DecreaseArgs &a, const SlotView &sv, Shared &sh, bo
         sh.qpre[tid] = ex;
         __syncthreads();
         const int cnt = min(kBlock, hi - base);
-        for (int q = tid; q < total; q += kBlock) {
-            int l = 0, h = cnt - 1;
-            while (l < h) {
-                const int mid = (l + h + 1) >> 1;
-                if (sh.qpre[mid] <= q) l = mid;
-                else h = mid - 1;
-            }
-            const int e0 = sh.e0[l], e1 = sh.e1[l], src = sh.src[l];
-            const int quad = (e0 >> 2) + (q - sh.qpre[l]);
-            const uint4 p01 = a.edges[2 * (size_t)quad];
-            const uint4 p23 = a.edges[2 * (size_t)quad + 1];
-            uint32_t w0, w1, w2, w3;
-            philox4x32_10((uint32_t)quad, j, a.key_lo, a.key_hi, w0, w1, w2, w3);
-            const int eb = quad * 4;
-            const uint32_t wv[4] = {w0, w1, w2, w3};
-            const uint32_t cv[4] = {p01.x, p01.z, p23.x, p23.z};
-            const uint32_t tv[4] = {p01.y, p01.w, p23.y, p23.w};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int e = eb + i;
-                if (e < e0 || e >= e1) continue;
-                if ((wv[i] >> 8) >= tv[i]) continue;
-                const int c = (int)cv[i];
-                if (bit_set(a.inelig, c)) continue;
-                ++live;
-                visit(a, sv, sh, c, src, epoch);
-            }
+        for (int q = tid; q < total; q += 2 * kBlock) {
+            const int q2 = q + kBlock;
+            const bool has2 = q2 < total;
+            int l1, quad1, l2, quad2;
+            locate(sh, cnt, q, l1, quad1);
+            locate(sh, cnt, has2 ? q2 : q, l2, quad2);
+            const uint4 a01 = a.edges[2 * (size_t)quad1];
+            const uint4 a23 = a.edges[2 * (size_t)quad1 + 1];
+            const uint4 b01 = a.edges[2 * (size_t)quad2];
+            const uint4 b23 = a.edges[2 * (size_t)quad2 + 1];
+            const uint32_t m1 = quad_mask(a, quad1, j, sh.e0[l1], sh.e1[l1], a01, a23);
+            const uint32_t m2 = has2 ? quad_mask(a, quad2, j, sh.e0[l2], sh.e1[l2], b01, b23) : 0u;
+            visit_mask(a, sv, sh, m1, a01, a23, from_seeds ? 0 : base + l1, epoch, live);
+            visit_mask(a, sv, sh, m2, b01, b23, from_seeds ? 0 : base + l2, epoch, live);
         }
         __syncthreads();
     }
 }
 
-__device__ __forceinline__ int nca(const int32_t *t, int x, int y)
+__device__ __forceinline__ int nca(const LocalVtx *t, int x, int y)
 {
     while (x != y) {
-        if (x > y) x = t[x];
-        else y = t[y];
+        if (x > y) x = t[x].tdom;
+        else y = t[y].tdom;
     }
     return x;
 }
 
-__global__ __launch_bounds__(kBlock) void decrease_kernel(DecreaseArgs a)
+// Sum of a per-thread value over the wave, added into an LDS counter by lane 0.
+__device__ __forceinline__ void wave_add(unsigned *dst, uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void decrease_kernel(DecreaseArgs a)
 {
     __shared__ Shared sh;
     const int tid = threadIdx.x;
     const size_t slot = blockIdx.x;
     SlotView sv;
     sv.map = a.ws.map + slot * (size_t)a.n;
-    sv.glob = a.ws.glob + slot * (size_t)a.ws.lcap;
-    sv.par0 = a.ws.par0 + slot * (size_t)a.ws.lcap;
-    sv.tdom = a.ws.tdom + slot * (size_t)a.ws.lcap;
-    sv.tnew = a.ws.tnew + slot * (size_t)a.ws.lcap;
-    sv.csz = a.ws.csz + slot * (size_t)a.ws.lcap;
+    sv.loc = a.ws.loc + slot * (size_t)a.ws.lcap;
     sv.lvl = a.ws.lvl + slot * (size_t)(a.ws.lcap + 1);
     sv.extra = a.ws.extra + slot * (size_t)a.ws.xcap;
     uint32_t epoch = a.ws.epoch[slot];
     const uint32_t count = a.sample_list ? *a.sample_count : a.theta;
-
-    unsigned long long t_samples = 0, t_reached = 0, t_scanned = 0, t_live = 0;
 
     for (;;) {
         if (tid == 0) sh.idx = atomicAdd(a.next, 1u);
@@ -223,16 +259,20 @@ __global__ __launch_bounds__(kBlock) void decrease_kernel(DecreaseArgs a)
             sh.tail = 1;
             sh.nextra = 0;
             sh.ovf = 0;
+            sh.scanned = 0;
+            sh.live = 0;
             sv.lvl[0] = 0;
             sv.lvl[1] = 1;
-            sv.glob[0] = -1;
-            sv.par0[0] = 0;
-            sv.tdom[0] = 0;
-            sv.csz[0] = 0;
+            LocalVtx root;
+            root.glob = -1;
+            root.par0 = 0;
+            root.tdom = 0;
+            root.csz = 0;
+            sv.loc[0] = root;
         }
         __syncthreads();
 
-        unsigned long long p_scanned = 0, p_live = 0;
+        uint32_t p_scanned = 0, p_live = 0;
         expand(a, sv, sh, true, 0, a.nseeds, j, epoch, p_scanned, p_live);
         int L = 1, lo = 1;
         int hi = sh.tail;
@@ -258,6 +298,8 @@ __global__ __launch_bounds__(kBlock) void decrease_kernel(DecreaseArgs a)
             }
             continue;
         }
+        wave_add(&sh.scanned, p_scanned);
+        wave_add(&sh.live, p_live);
         const int nV = sh.tail;
         const int nX = sh.nextra;
 
@@ -270,30 +312,32 @@ __global__ __launch_bounds__(kBlock) void decrease_kernel(DecreaseArgs a)
         __syncthreads();
 
         // Dominator tree: Jacobi NCA steps over vertices with several reached predecessors.
+        // The subtree-size field of such a vertex holds the next tentative dominator
+        // meanwhile, and is reset to 1 afterwards.
         if (nX > 0) {
             for (;;) {
                 for (int x = tid; x < nX; x += kBlock) {
                     const int v = sv.extra[x].y;
-                    sv.tnew[v] = sv.tdom[v];
+                    sv.loc[v].csz = sv.loc[v].tdom;
                 }
                 if (tid == 0) sh.changed = 0;
                 __syncthreads();
                 for (int x = tid; x < nX; x += kBlock) {
                     const int2 e = sv.extra[x];
-                    const int tv = sv.tdom[e.y];
-                    const int m1 = nca(sv.tdom, tv, e.x);
-                    const int m2 = nca(sv.tdom, tv, sv.par0[e.y]);
+                    const int tv = sv.loc[e.y].tdom;
+                    const int m1 = nca(sv.loc, tv, e.x);
+                    const int m2 = nca(sv.loc, tv, sv.loc[e.y].par0);
                     const int mm = min(m1, m2);
                     if (mm < tv)
-                        __hip_atomic_fetch_min(&sv.tnew[e.y], mm, __ATOMIC_RELAXED,
+                        __hip_atomic_fetch_min(&sv.loc[e.y].csz, mm, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
                 __syncthreads();
                 for (int x = tid; x < nX; x += kBlock) {
                     const int v = sv.extra[x].y;
-                    const int nv = sv.tnew[v];
-                    if (nv != sv.tdom[v]) {
-                        sv.tdom[v] = nv;
+                    const int nv = sv.loc[v].csz;
+                    if (nv != sv.loc[v].tdom) {
+                        sv.loc[v].tdom = nv;
                         sh.changed = 1;
                     }
                 }
@@ -302,33 +346,30 @@ __global__ __launch_bounds__(kBlock) void decrease_kernel(DecreaseArgs a)
                 __syncthreads();
                 if (!ch) break;
             }
+            for (int x = tid; x < nX; x += kBlock) sv.loc[sv.extra[x].y].csz = 1;
+            __syncthreads();
         }
 
         // Subtree sizes, deepest BFS level first, and the exact accumulation into D.
         for (int l = L - 1; l >= 1; --l) {
             const int b0 = sv.lvl[l], b1 = sv.lvl[l + 1];
             for (int i = b0 + tid; i < b1; i += kBlock) {
-                const int c = sv.csz[i];
-                const int p = sv.tdom[i];
-                if (p != 0)
-                    __hip_atomic_fetch_add(&sv.csz[p], c, __ATOMIC_RELAXED,
+                const LocalVtx r = sv.loc[i];
+                if (r.tdom != 0)
+                    __hip_atomic_fetch_add(&sv.loc[r.tdom].csz, r.csz, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
-                atomicAdd(&a.D[sv.glob[i]], (unsigned long long)c);
+                atomicAdd(&a.D[r.glob], (unsigned long long)r.csz);
             }
             __syncthreads();
         }
-        t_scanned += p_scanned;
-        t_live += p_live;
         if (tid == 0) {
-            t_samples += 1;
-            t_reached += (unsigned long long)(nV - 1);
+            atomicAdd(&a.stats[0], 1ull);
+            atomicAdd(&a.stats[1], (unsigned long long)(nV - 1));
+            atomicAdd(&a.stats[2], (unsigned long long)sh.scanned);
+            atomicAdd(&a.stats[3], (unsigned long long)sh.live);
         }
     }
     if (tid == 0) a.ws.epoch[slot] = epoch;
-    if (t_samples) atomicAdd(&a.stats[0], t_samples);
-    if (t_reached) atomicAdd(&a.stats[1], t_reached);
-    if (t_scanned) atomicAdd(&a.stats[2], t_scanned);
-    if (t_live) atomicAdd(&a.stats[3], t_live);
 }
 
 }  // namespace

@@ -6,27 +6,36 @@
 
 namespace imin {
 
-constexpr int kBlock = 256;  // threads per workgroup; one workgroup works on one sample at a time
+constexpr int kBlock = 1024;  // threads per workgroup; one workgroup works on one sample at a time
 
 // Per slot and vertex: the epoch of the sample that last reached the vertex, and its
 // local id in that sample. Both halves live in one 8-byte entry so a lookup touches one line.
+// A stamp of kInelig marks a seed or a blocked vertex: it never becomes a visit, and an
+// atomic max with the current epoch both tests eligibility and claims the vertex.
+constexpr uint32_t kInelig = 0xFFFFFFFFu;
 struct SlotEntry {
     uint32_t stamp;
     int32_t lid;
 };
 
+// Per slot and local vertex (local id 0 is the merged seed): the vertex id, the parent in
+// the BFS spanning tree, the tentative immediate dominator and the subtree size. One
+// 16-byte record, written once when the vertex is reached.
+struct LocalVtx {
+    int32_t glob;
+    int32_t par0;
+    int32_t tdom;
+    int32_t csz;
+};
+
 // Scratch of `slots` concurrent samples. Arrays are slot-major: slot s owns
-// [s * n, (s + 1) * n) of `map`, [s * lcap, (s + 1) * lcap) of the local arrays, and so on.
+// [s * n, (s + 1) * n) of `map`, [s * lcap, (s + 1) * lcap) of `loc`, and so on.
 struct Workspace {
     int32_t slots = 0;
-    int64_t lcap = 0;        // local vertices per sample (root included)
-    int64_t xcap = 0;        // non-tree live edges per sample
+    int64_t lcap = 0;          // local vertices per sample (root included)
+    int64_t xcap = 0;          // non-tree live edges per sample
     SlotEntry *map = nullptr;  // slots * n
-    int32_t *glob = nullptr;   // slots * lcap: local id -> vertex id
-    int32_t *par0 = nullptr;   // slots * lcap: parent in the BFS spanning tree
-    int32_t *tdom = nullptr;   // slots * lcap: tentative immediate dominator
-    int32_t *tnew = nullptr;   // slots * lcap: next value of tdom (Jacobi step)
-    int32_t *csz = nullptr;    // slots * lcap: dominator-subtree sizes
+    LocalVtx *loc = nullptr;   // slots * lcap
     int32_t *lvl = nullptr;    // slots * (lcap + 1): first local id of each BFS level
     int2 *extra = nullptr;     // slots * xcap: (source local id, target vertex -> local id)
     uint32_t *epoch = nullptr; // slots
@@ -38,7 +47,6 @@ struct Workspace {
 struct DecreaseArgs {
     const int32_t *row_ptr;  // n + 1
     const uint4 *edges;      // ceil(m / 4) * 2 uint4: (col, thr) pairs, 4 edges = 32 bytes
-    const uint32_t *inelig;  // bitmap over vertices: seed or blocked
     const int32_t *seeds;    // distinct seeds
     int32_t nseeds;
     int32_t n;
@@ -71,5 +79,14 @@ hipError_t launch_argmax_apply(const unsigned long long *D, const uint32_t *bits
                                int32_t parts, uint32_t *inelig, uint32_t *cand, int32_t *B,
                                int32_t slot, int32_t *out_x, hipStream_t stream);
 hipError_t launch_set_bit(uint32_t *bits, int32_t v, int value, hipStream_t stream);
+// Stamps of the slot maps: every vertex whose bit is set in `bits` becomes kInelig in all
+// slots; or the vertices of `list` (device) get `value`; or one vertex (host value, or the
+// device-resident id at `v_dev`, ignored when negative) gets `value`.
+hipError_t launch_mark_bitmap(SlotEntry *map, int32_t slots, int32_t n, const uint32_t *bits,
+                              hipStream_t stream);
+hipError_t launch_set_stamps(SlotEntry *map, int32_t slots, int32_t n, const int32_t *list,
+                             int32_t count, uint32_t value, hipStream_t stream);
+hipError_t launch_set_stamp(SlotEntry *map, int32_t slots, int32_t n, int32_t v,
+                            const int32_t *v_dev, uint32_t value, hipStream_t stream);
 
 }  // namespace imin

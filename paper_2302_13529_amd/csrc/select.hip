@@ -95,6 +95,40 @@ __global__ void set_bit_kernel(uint32_t *bits, int32_t v, int value)
     else bits[v >> 5] &= ~(1u << (v & 31));
 }
 
+__global__ void mark_bitmap_kernel(SlotEntry *map, int32_t slots, int32_t n, const uint32_t *bits)
+{
+    const int32_t words = (n + 31) / 32;
+    for (int32_t w = blockIdx.x * kSelBlock + threadIdx.x; w < words; w += gridDim.x * kSelBlock) {
+        uint32_t b = bits[w];
+        while (b) {
+            const int32_t v = w * 32 + __builtin_ctz(b);
+            b &= b - 1;
+            for (int32_t s = 0; s < slots; ++s) map[(size_t)s * n + v].stamp = kInelig;
+        }
+    }
+}
+
+__global__ void set_stamps_kernel(SlotEntry *map, int32_t slots, int32_t n, const int32_t *list,
+                                  int32_t count, uint32_t value)
+{
+    const int64_t total = (int64_t)slots * count;
+    for (int64_t i = blockIdx.x * (int64_t)kSelBlock + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * kSelBlock) {
+        const int32_t s = (int32_t)(i / count);
+        const int32_t v = list[i % count];
+        map[(size_t)s * n + v].stamp = value;
+    }
+}
+
+__global__ void set_stamp_kernel(SlotEntry *map, int32_t slots, int32_t n, int32_t v,
+                                 const int32_t *v_dev, uint32_t value)
+{
+    const int32_t x = v_dev ? *v_dev : v;
+    if (x < 0) return;
+    for (int32_t s = blockIdx.x * kSelBlock + threadIdx.x; s < slots; s += gridDim.x * kSelBlock)
+        map[(size_t)s * n + x].stamp = value;
+}
+
 int grid_for(int64_t count)
 {
     int64_t g = (count + kSelBlock - 1) / kSelBlock;
@@ -135,6 +169,33 @@ hipError_t launch_argmax_apply(const unsigned long long *D, const uint32_t *bits
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(argmax_final_kernel, dim3(1), dim3(kSelBlock), 0, stream, part_d, part_i, g,
                        inelig, cand, B, slot, out_x);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_bitmap(SlotEntry *map, int32_t slots, int32_t n, const uint32_t *bits,
+                              hipStream_t stream)
+{
+    if (slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mark_bitmap_kernel, dim3(grid_for((n + 31) / 32)), dim3(kSelBlock), 0,
+                       stream, map, slots, n, bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_stamps(SlotEntry *map, int32_t slots, int32_t n, const int32_t *list,
+                             int32_t count, uint32_t value, hipStream_t stream)
+{
+    if (slots <= 0 || count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(set_stamps_kernel, dim3(grid_for((int64_t)slots * count)), dim3(kSelBlock),
+                       0, stream, map, slots, n, list, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_stamp(SlotEntry *map, int32_t slots, int32_t n, int32_t v,
+                            const int32_t *v_dev, uint32_t value, hipStream_t stream)
+{
+    if (slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(set_stamp_kernel, dim3(grid_for(slots)), dim3(kSelBlock), 0, stream, map,
+                       slots, n, v, v_dev, value);
     return hipGetLastError();
 }
 
