@@ -14,6 +14,7 @@ same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -33,18 +34,24 @@ def algorithmic_bytes(stats: dict, n_seeds: int) -> float:
     return 8.0 * expanded + 8.0 * stats["edges_scanned"] + 8.0 * stats["reached"]
 
 
-def traffic_from_profile(path: str):
-    """HBM bytes per launch from a committed counter summary, when one exists."""
+def traffic_from_profile(path: str, kernel_source: str):
+    """HBM bytes per launch from the committed counter summary, or None when there is none
+    or when the kernel source changed since the counters were taken."""
     if not os.path.exists(path):
         return None
-    try:
-        with open(path) as f:
-            for line in f:
-                if line.startswith("traffic_bytes_per_launch:"):
-                    return float(line.split(":", 1)[1])
-    except OSError:
+    digest = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.split()[0] if v.split() else ""
+    if fields.get("kernel_source_sha256") != digest:
         return None
-    return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(inst, theta_sample: int) -> dict:
@@ -97,7 +104,9 @@ def main() -> int:
     alg = algorithmic_bytes(st, len(inst.seeds))
     kernel_s = st["kernel_ms"] / 1e3
     achieved = alg / kernel_s / 1e9
-    traffic = traffic_from_profile(os.path.join(ROOT, "profiles", "decrease_kernel_rmat22_pmc.txt"))
+    traffic = traffic_from_profile(
+        os.path.join(ROOT, "profiles", "decrease_kernel_rmat22_pmc.txt"),
+        os.path.join(ROOT, "paper_2302_13529_amd", "csrc", "decrease.hip"))
     out = {
         "metric": "live-edge samples/sec incl. dominator decrease",
         "value": samples / dt,
