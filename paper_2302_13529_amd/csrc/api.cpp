@@ -21,7 +21,8 @@ struct imin_graph {
     std::vector<int32_t> row_ptr;  // host copies: out-neighbours of the seeds (GR)
     std::vector<int32_t> col;
     int32_t *d_row_ptr = nullptr;
-    uint4 *d_edges = nullptr;
+    uint4 *d_col4 = nullptr;   // edge targets, 4 per quad, padded to a whole quad
+    uint4 *d_thr4 = nullptr;   // live thresholds, same layout
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int32_t words = 0;                       // 32-bit words of a vertex bitmap
@@ -289,7 +290,8 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key)
     DecreaseArgs a;
     std::memset(&a, 0, sizeof(a));
     a.row_ptr = g->d_row_ptr;
-    a.edges = g->d_edges;
+    a.col4 = g->d_col4;
+    a.thr4 = g->d_thr4;
     a.seeds = g->d_seeds;
     a.nseeds = nseeds;
     a.n = g->n;
@@ -370,7 +372,8 @@ void destroy(imin_graph *g)
     free_ws(g->main_ws);
     free_ws(g->big_ws);
     dfree(g->d_row_ptr);
-    dfree(g->d_edges);
+    dfree(g->d_col4);
+    dfree(g->d_thr4);
     dfree(g->d_inelig);
     dfree(g->d_cand);
     dfree(g->d_seeds);
@@ -443,24 +446,26 @@ int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
         delete g;
         return IMIN_ENOMEM;
     }
-    const int64_t quads = ((int64_t)m + 3) / 4;
-    std::vector<uint32_t> packed;
+    const int64_t quads = std::max<int64_t>(((int64_t)m + 3) / 4, 1);
+    std::vector<uint32_t> hcol, hthr;
     try {
-        packed.assign((size_t)std::max<int64_t>(quads, 1) * 8, 0u);
+        hcol.assign((size_t)quads * 4, 0u);
+        hthr.assign((size_t)quads * 4, 0u);  // padding edges have threshold 0: never live
     } catch (...) {
         delete g;
         return IMIN_ENOMEM;
     }
     for (int32_t e = 0; e < m; ++e) {
-        packed[2 * (size_t)e] = (uint32_t)col[e];
-        packed[2 * (size_t)e + 1] = live_threshold(prob[e]);
+        hcol[(size_t)e] = (uint32_t)col[e];
+        hthr[(size_t)e] = live_threshold(prob[e]);
     }
     g->words = (n + 31) / 32;
     bool good =
         ok(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking)) &&
         ok(hipEventCreate(&g->ev0)) && ok(hipEventCreate(&g->ev1)) &&
         ok(hipMalloc(&g->d_row_ptr, (size_t)(n + 1) * sizeof(int32_t))) &&
-        ok(hipMalloc(&g->d_edges, packed.size() * sizeof(uint32_t))) &&
+        ok(hipMalloc(&g->d_col4, hcol.size() * sizeof(uint32_t))) &&
+        ok(hipMalloc(&g->d_thr4, hthr.size() * sizeof(uint32_t))) &&
         ok(hipMalloc(&g->d_inelig, (size_t)g->words * sizeof(uint32_t))) &&
         ok(hipMalloc(&g->d_cand, (size_t)g->words * sizeof(uint32_t))) &&
         ok(hipMalloc(&g->d_seeds, (size_t)n * sizeof(int32_t))) &&
@@ -478,7 +483,9 @@ int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
     }
     if (!ok(hipMemcpy(g->d_row_ptr, row_ptr, (size_t)(n + 1) * sizeof(int32_t),
                       hipMemcpyHostToDevice)) ||
-        !ok(hipMemcpy(g->d_edges, packed.data(), packed.size() * sizeof(uint32_t),
+        !ok(hipMemcpy(g->d_col4, hcol.data(), hcol.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice)) ||
+        !ok(hipMemcpy(g->d_thr4, hthr.data(), hthr.size() * sizeof(uint32_t),
                       hipMemcpyHostToDevice))) {
         destroy(g);
         return IMIN_EDEVICE;

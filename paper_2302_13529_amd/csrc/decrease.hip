@@ -148,34 +148,35 @@ __device__ __forceinline__ void locate(const Shared &sh, int cnt, int q, int &l,
 // Live-edge bits of one quad for sample j: bit i set when edge 4*quad+i lies in [e0, e1)
 // and its coin falls under its threshold.
 __device__ __forceinline__ uint32_t quad_mask(const DecreaseArgs &a, int quad, uint32_t j, int e0,
-                                              int e1, uint4 p01, uint4 p23)
+                                              int e1, uint4 thr)
 {
     uint32_t w0, w1, w2, w3;
     philox4x32_10((uint32_t)quad, j, a.key_lo, a.key_hi, w0, w1, w2, w3);
     const int eb = quad * 4;
     uint32_t mask = 0;
-    mask |= (eb + 0 >= e0 && eb + 0 < e1 && (w0 >> 8) < p01.y) ? 1u : 0u;
-    mask |= (eb + 1 >= e0 && eb + 1 < e1 && (w1 >> 8) < p01.w) ? 2u : 0u;
-    mask |= (eb + 2 >= e0 && eb + 2 < e1 && (w2 >> 8) < p23.y) ? 4u : 0u;
-    mask |= (eb + 3 >= e0 && eb + 3 < e1 && (w3 >> 8) < p23.w) ? 8u : 0u;
+    mask |= (eb + 0 >= e0 && eb + 0 < e1 && (w0 >> 8) < thr.x) ? 1u : 0u;
+    mask |= (eb + 1 >= e0 && eb + 1 < e1 && (w1 >> 8) < thr.y) ? 2u : 0u;
+    mask |= (eb + 2 >= e0 && eb + 2 < e1 && (w2 >> 8) < thr.z) ? 4u : 0u;
+    mask |= (eb + 3 >= e0 && eb + 3 < e1 && (w3 >> 8) < thr.w) ? 8u : 0u;
     return mask;
 }
 
 __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView &sv, Shared &sh,
-                                           uint32_t mask, uint4 p01, uint4 p23, int src,
-                                           uint32_t epoch, uint32_t &live)
+                                           uint32_t mask, uint4 col, int src, uint32_t epoch,
+                                           uint32_t &live)
 {
     while (mask) {
         const int i = __builtin_ctz(mask);
         mask &= mask - 1;
-        const uint32_t c = i == 0 ? p01.x : i == 1 ? p01.z : i == 2 ? p23.x : p23.z;
+        const uint32_t c = i == 0 ? col.x : i == 1 ? col.y : i == 2 ? col.z : col.w;
         if (visit(a, sv, sh, (int)c, src, epoch)) ++live;
     }
 }
 
 // Expand the frontier [lo, hi): seeds (from_seeds, source = merged root 0) or local ids.
 // The frontier goes in chunks of kBlock entries; the edge quads of a chunk are spread
-// evenly over the workgroup, two independent quads in flight per thread.
+// evenly over the workgroup, two independent quads in flight per thread. A quad's
+// thresholds are always read; its targets only when one of its coins comes up live.
 __device__ void expand(const DecreaseArgs &a, const SlotView &sv, Shared &sh, bool from_seeds,
                        int lo, int hi, uint32_t j, uint32_t epoch, uint32_t &scanned,
                        uint32_t &live)
@@ -204,14 +205,15 @@ __device__ void expand(const DecreaseArgs &a, const SlotView &sv, Shared &sh, bo
             int l1, quad1, l2, quad2;
             locate(sh, cnt, q, l1, quad1);
             locate(sh, cnt, has2 ? q2 : q, l2, quad2);
-            const uint4 a01 = a.edges[2 * (size_t)quad1];
-            const uint4 a23 = a.edges[2 * (size_t)quad1 + 1];
-            const uint4 b01 = a.edges[2 * (size_t)quad2];
-            const uint4 b23 = a.edges[2 * (size_t)quad2 + 1];
-            const uint32_t m1 = quad_mask(a, quad1, j, sh.e0[l1], sh.e1[l1], a01, a23);
-            const uint32_t m2 = has2 ? quad_mask(a, quad2, j, sh.e0[l2], sh.e1[l2], b01, b23) : 0u;
-            visit_mask(a, sv, sh, m1, a01, a23, from_seeds ? 0 : base + l1, epoch, live);
-            visit_mask(a, sv, sh, m2, b01, b23, from_seeds ? 0 : base + l2, epoch, live);
+            const uint4 t1 = a.thr4[quad1];
+            const uint4 t2 = a.thr4[quad2];
+            const uint32_t m1 = quad_mask(a, quad1, j, sh.e0[l1], sh.e1[l1], t1);
+            const uint32_t m2 = has2 ? quad_mask(a, quad2, j, sh.e0[l2], sh.e1[l2], t2) : 0u;
+            uint4 c1 = make_uint4(0, 0, 0, 0), c2 = make_uint4(0, 0, 0, 0);
+            if (m1) c1 = a.col4[quad1];
+            if (m2) c2 = a.col4[quad2];
+            visit_mask(a, sv, sh, m1, c1, from_seeds ? 0 : base + l1, epoch, live);
+            visit_mask(a, sv, sh, m2, c2, from_seeds ? 0 : base + l2, epoch, live);
         }
         __syncthreads();
     }

@@ -46,7 +46,8 @@ struct Workspace {
 // Everything one launch of the decrease kernel reads or writes.
 struct DecreaseArgs {
     const int32_t *row_ptr;  // n + 1
-    const uint4 *edges;      // ceil(m / 4) * 2 uint4: (col, thr) pairs, 4 edges = 32 bytes
+    const uint4 *col4;       // ceil(m / 4) quads of edge targets (4 edges = 16 bytes)
+    const uint4 *thr4;       // ceil(m / 4) quads of live thresholds ceil(p * 2^24)
     const int32_t *seeds;    // distinct seeds
     int32_t nseeds;
     int32_t n;
