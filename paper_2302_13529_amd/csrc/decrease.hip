@@ -87,10 +87,14 @@ struct SlotView {
     int2 *extra;
 };
 
+// Frontier entries per chunk: each thread prepares kPerThread consecutive entries.
+constexpr int kPerThread = 4;
+constexpr int kChunk = kBlock * kPerThread;
+
 struct Shared {
-    int e0[kBlock];
-    int e1[kBlock];
-    int qpre[kBlock + 1];
+    int e0[kChunk];
+    int e1[kChunk];
+    int qpre[kChunk + 1];
     int wave[kBlock / 64];
     unsigned idx;
     int tail;
@@ -174,31 +178,43 @@ __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView
 }
 
 // Expand the frontier [lo, hi): seeds (from_seeds, source = merged root 0) or local ids.
-// The frontier goes in chunks of kBlock entries; the edge quads of a chunk are spread
-// evenly over the workgroup, two independent quads in flight per thread. A quad's
-// thresholds are always read; its targets only when one of its coins comes up live.
+// The frontier goes in chunks of kChunk entries (kPerThread consecutive entries per thread);
+// the edge quads of a chunk are spread evenly over the workgroup, two independent quads in
+// flight per thread. A quad's thresholds are always read; its targets only when one of its
+// coins comes up live.
 __device__ void expand(const DecreaseArgs &a, const SlotView &sv, Shared &sh, bool from_seeds,
                        int lo, int hi, uint32_t j, uint32_t epoch, uint32_t &scanned,
                        uint32_t &live)
 {
     const int tid = threadIdx.x;
-    for (int base = lo; base < hi; base += kBlock) {
-        const int k = base + tid;
-        int nq = 0;
-        if (k < hi) {
-            const int v = from_seeds ? a.seeds[k] : sv.loc[k].glob;
-            const int e0 = a.row_ptr[v];
-            const int e1 = a.row_ptr[v + 1];
-            scanned += (uint32_t)(e1 - e0);
-            nq = (e1 > e0) ? (((e1 - 1) >> 2) - (e0 >> 2) + 1) : 0;
-            sh.e0[tid] = e0;
-            sh.e1[tid] = e1;
+    for (int base = lo; base < hi; base += kChunk) {
+        const int first = tid * kPerThread;
+        int nq[kPerThread];
+        int mine = 0;
+#pragma unroll
+        for (int i = 0; i < kPerThread; ++i) {
+            const int k = base + first + i;
+            nq[i] = 0;
+            if (k < hi) {
+                const int v = from_seeds ? a.seeds[k] : sv.loc[k].glob;
+                const int e0 = a.row_ptr[v];
+                const int e1 = a.row_ptr[v + 1];
+                scanned += (uint32_t)(e1 - e0);
+                nq[i] = (e1 > e0) ? (((e1 - 1) >> 2) - (e0 >> 2) + 1) : 0;
+                sh.e0[first + i] = e0;
+                sh.e1[first + i] = e1;
+            }
+            mine += nq[i];
         }
         int total;
-        const int ex = block_exclusive_scan(nq, sh.wave, &total);
-        sh.qpre[tid] = ex;
+        int ex = block_exclusive_scan(mine, sh.wave, &total);
+#pragma unroll
+        for (int i = 0; i < kPerThread; ++i) {
+            sh.qpre[first + i] = ex;
+            ex += nq[i];
+        }
         __syncthreads();
-        const int cnt = min(kBlock, hi - base);
+        const int cnt = min(kChunk, hi - base);
         for (int q = tid; q < total; q += 2 * kBlock) {
             const int q2 = q + kBlock;
             const bool has2 = q2 < total;
