@@ -73,6 +73,8 @@ typedef struct {
     double device_ms;       /* GPU time of the whole call, measured with HIP events */
     double kernel_ms;       /* GPU time of the sampling/dominator kernel launches alone,
                                summed over the call (HIP events around each launch) */
+    uint64_t wave_samples;  /* samples finished by the one-wave-per-sample kernel (the rest
+                               ran one workgroup per sample) */
 } imin_stats;
 
 /*
@@ -143,6 +145,51 @@ IMIN_API int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b,
  * check that, and to tune. Errors: IMIN_EINVAL for negative values or NULL g.
  */
 IMIN_API int imin_set_launch(imin_graph *g, int32_t slots, int64_t extra_cap);
+
+/*
+ * imin_set_small -- launch policy of the one-wave-per-sample kernel for later calls on g.
+ * Every sample first runs in one wavefront with LDS-resident state; a sample that reaches
+ * more than 255 vertices, keeps more than 256 non-tree live edges, or meets a 64-vertex
+ * frontier chunk with more than quad_limit 4-edge quads is left, with nothing accumulated,
+ * to the one-workgroup-per-sample kernel in the same call.
+ *   enable        -1 automatic (the default: on, and switched off for g once fewer than
+ *                 half of a round's samples finish in the wave kernel), 0 off, 1 on.
+ *   waves_per_cu  resident waves per compute unit for the wave kernel (0: default 20).
+ *   quad_limit    as above (0: default 2048).
+ * Results never depend on these values. Errors: IMIN_EINVAL for NULL g, enable outside
+ * [-1, 1], or negative sizes.
+ */
+IMIN_API int imin_set_small(imin_graph *g, int32_t enable, int32_t waves_per_cu,
+                            int32_t quad_limit);
+
+/*
+ * One problem of a batched greedy call (imin_greedy_batch); the fields mean what the
+ * arguments of imin_greedy mean. Outputs are written only when the whole batch succeeds.
+ */
+typedef struct {
+    imin_graph *g;          /* the instance's graph; distinct across one batch */
+    const int32_t *S;       /* host int32[nS] seed set */
+    int32_t nS;
+    int32_t b;              /* budget, b >= 0 */
+    uint32_t theta;         /* samples per round, >= 1 */
+    uint64_t seed;          /* round r uses Philox key seed + r */
+    int32_t *blockers;      /* out: host int32[b] */
+    int32_t *n_blockers;    /* out */
+    imin_stats *stats;      /* out, may be NULL; device_ms and kernel_ms are the batch's */
+} imin_instance;
+
+/*
+ * imin_greedy_batch -- AdvancedGreedy (Algorithm 3) on `count` independent problems at once.
+ * Round r of every instance that still has rounds left runs in the same launches: one
+ * wave-per-sample launch over all their samples (samples that outgrow it go to the
+ * workgroup kernel of their own graph), then one argmax per instance. Instance i's result
+ * is bit-identical to imin_greedy(inst[i].g, S, nS, b, theta, seed, IMIN_AG, ...).
+ *   mode   IMIN_AG only (IMIN_EINVAL otherwise).
+ *   count  >= 1; the total of theta over the batch must stay below 2^31 (IMIN_ERANGE).
+ * Errors: IMIN_EINVAL (any instance invalid as for imin_greedy, a graph repeated, NULL
+ * inst), IMIN_ERANGE, IMIN_ENOMEM, IMIN_EDEVICE.
+ */
+IMIN_API int imin_greedy_batch(imin_instance *inst, int32_t count, int mode);
 
 /* Human-readable text of a status code (static storage). */
 IMIN_API const char *imin_strerror(int status);

@@ -1,9 +1,10 @@
 """ctypes binding of libimin (include/imin.h): argument marshalling only.
 
 The functions keep the C names (``imin_graph_create``, ``imin_decrease``, ``imin_greedy``,
-``imin_set_launch``, ``imin_graph_destroy``, ``imin_strerror``); ``Graph`` wraps them for
-convenience. Every step of the estimate runs in the library's HIP kernels; if the library
-is missing this module raises instead of computing anything itself.
+``imin_greedy_batch``, ``imin_set_launch``, ``imin_set_small``, ``imin_graph_destroy``,
+``imin_strerror``); ``Graph`` wraps them for convenience. Every step of the estimate runs in
+the library's HIP kernels; if the library is missing this module raises instead of
+computing anything itself.
 """
 from __future__ import annotations
 
@@ -29,10 +30,17 @@ class imin_stats(ctypes.Structure):
     _fields_ = [("samples", ctypes.c_uint64), ("reached", ctypes.c_uint64),
                 ("edges_scanned", ctypes.c_uint64), ("live_edges", ctypes.c_uint64),
                 ("spilled", ctypes.c_uint64), ("device_ms", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double), ("wave_samples", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class imin_instance(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("S", ctypes.c_void_p), ("nS", ctypes.c_int32),
+                ("b", ctypes.c_int32), ("theta", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("blockers", ctypes.c_void_p), ("n_blockers", ctypes.c_void_p),
+                ("stats", ctypes.POINTER(imin_stats))]
 
 
 _lib = None
@@ -63,6 +71,11 @@ def load() -> ctypes.CDLL:
     lib.imin_greedy.restype = ctypes.c_int
     lib.imin_set_launch.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
     lib.imin_set_launch.restype = ctypes.c_int
+    lib.imin_set_small.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.imin_set_small.restype = ctypes.c_int
+    lib.imin_greedy_batch.argtypes = [ctypes.POINTER(imin_instance), ctypes.c_int32,
+                                      ctypes.c_int]
+    lib.imin_greedy_batch.restype = ctypes.c_int
     lib.imin_strerror.argtypes = [ctypes.c_int]
     lib.imin_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -100,6 +113,14 @@ def imin_set_launch(handle: int, slots: int = 0, extra_cap: int = 0) -> None:
         raise IminError("imin_set_launch", rc)
 
 
+def imin_set_small(handle: int, enable: int = -1, waves_per_cu: int = 0,
+                   quad_limit: int = 0) -> None:
+    rc = load().imin_set_small(ctypes.c_void_p(handle), int(enable), int(waves_per_cu),
+                               int(quad_limit))
+    if rc != IMIN_OK:
+        raise IminError("imin_set_small", rc)
+
+
 def imin_decrease(handle: int, n: int, seeds, blocked, theta: int, seed: int):
     """Exact counts D (uint64[n]) and the stats dict of one Algorithm 2 call."""
     S = np.ascontiguousarray(seeds, dtype=np.int32)
@@ -129,6 +150,35 @@ def imin_greedy(handle: int, seeds, b: int, theta: int, seed: int, mode: int):
     return out[: nb[0]].copy(), st.as_dict()
 
 
+def imin_greedy_batch(problems, mode: int = IMIN_AG):
+    """AdvancedGreedy on many problems at once. ``problems``: sequence of
+    (handle, seeds, b, theta, seed). Returns a list of (blockers, stats dict)."""
+    k = len(problems)
+    arr = (imin_instance * max(k, 1))()
+    keep = []
+    outs = []
+    for i, (handle, seeds, b, theta, seed) in enumerate(problems):
+        S = np.ascontiguousarray(seeds, dtype=np.int32)
+        out = np.zeros(max(int(b), 1), dtype=np.int32)
+        nb = np.zeros(1, dtype=np.int32)
+        st = imin_stats()
+        keep += [S, out, nb, st]
+        outs.append((out, nb, st))
+        arr[i].g = ctypes.c_void_p(handle)
+        arr[i].S = _p(S)
+        arr[i].nS = S.shape[0]
+        arr[i].b = int(b)
+        arr[i].theta = int(theta)
+        arr[i].seed = int(seed) & (2**64 - 1)
+        arr[i].blockers = _p(out)
+        arr[i].n_blockers = _p(nb)
+        arr[i].stats = ctypes.pointer(st)
+    rc = load().imin_greedy_batch(arr, k, int(mode))
+    if rc != IMIN_OK:
+        raise IminError("imin_greedy_batch", rc)
+    return [(out[: nb[0]].copy(), st.as_dict()) for out, nb, st in outs]
+
+
 class Graph:
     """A device-resident graph (one ``imin_graph`` handle)."""
 
@@ -145,6 +195,9 @@ class Graph:
 
     def set_launch(self, slots: int = 0, extra_cap: int = 0) -> None:
         imin_set_launch(self.handle, slots, extra_cap)
+
+    def set_small(self, enable: int = -1, waves_per_cu: int = 0, quad_limit: int = 0) -> None:
+        imin_set_small(self.handle, enable, waves_per_cu, quad_limit)
 
     def close(self) -> None:
         if self.handle:

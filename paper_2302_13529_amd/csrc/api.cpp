@@ -5,6 +5,7 @@
 #include "imin_internal.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -30,8 +31,18 @@ struct imin_graph {
     uint32_t *d_cand = nullptr;              // GR candidate set CB
     int32_t *d_seeds = nullptr;              // distinct seeds (capacity n)
     unsigned long long *d_D = nullptr;       // n
-    unsigned long long *d_stats = nullptr;   // 5: samples, reached, scanned, live, spilled
+    unsigned long long *d_stats = nullptr;   // kStats: samples, reached, scanned, live,
+                                             // spilled, wave-kernel samples
     uint32_t *d_ctrl = nullptr;              // 4: next main, next spill, spill count, error
+    uint32_t *d_sctrl = nullptr;             // 2: wave-kernel work counter, samples it left
+    uint32_t *d_sj = nullptr;                // samples the wave kernel left to the large one
+    uint32_t sj_cap = 0;
+    imin::InstanceDesc *d_inst = nullptr;    // this graph as the one instance of a wave launch
+    imin::InstanceDesc h_inst{};
+    int small_mode = -1;                     // wave kernel: -1 automatic, 0 off, 1 on
+    bool small_auto_off = false;             // automatic mode found most samples too large
+    int32_t small_waves_per_cu = 0;          // 0: default
+    int32_t quad_limit = 0;                  // 0: default
     uint32_t *d_ovf = nullptr;
     uint32_t ovf_cap = 0;
     unsigned long long *d_part_d = nullptr;
@@ -53,6 +64,12 @@ struct imin_graph {
 namespace {
 
 constexpr uint32_t kSpillSlots = 2;
+constexpr int kStats = 6;
+constexpr int32_t kDefaultSmallWavesPerCu = 20;
+constexpr int32_t kDefaultQuadLimit = 2048;
+// In automatic mode the wave kernel is dropped for a graph once fewer than this share of
+// a round's samples finished in it.
+constexpr double kSmallKeepShare = 0.5;
 // The per-launch work counter is 32-bit and every workgroup takes one index past the end.
 constexpr uint32_t kMaxTheta = 1u << 31;
 
@@ -120,7 +137,8 @@ int alloc_ws(imin_graph *g, Workspace &ws, int32_t slots, int64_t lcap, int64_t 
 // Per-slot scratch: every local array holds all n vertices plus the root, so only the
 // extra-edge list can overflow. Its default capacity covers a quarter of the vertices; a
 // graph whose m is below that can never overflow and needs no spill path.
-int prepare_workspaces(imin_graph *g)
+// After a call that stopped half-way the slot-map stamps are unknown: drop the scratch.
+void reset_stale(imin_graph *g)
 {
     if (!g->marks_valid) {
         free_ws(g->main_ws);
@@ -128,6 +146,11 @@ int prepare_workspaces(imin_graph *g)
         g->marked.clear();
         g->marks_valid = true;
     }
+}
+
+// max_slots > 0 caps a new allocation (an existing one of the right shape is kept).
+int size_workspaces(imin_graph *g, int32_t max_slots)
+{
     const int64_t lcap = (int64_t)g->n + 1;
     const int64_t xmax = (int64_t)g->m + 1;
     int64_t xcap = g->force_xcap > 0 ? g->force_xcap
@@ -141,8 +164,9 @@ int prepare_workspaces(imin_graph *g)
         const size_t per = slot_bytes(g->n, lcap, xcap);
         const size_t by_mem = std::max<size_t>(1, (free_b / 2) / per);
         slots = (int32_t)std::min<size_t>((size_t)2 * g->num_cus, by_mem);
+        if (max_slots > 0) slots = std::min(slots, max_slots);
         if (g->main_ws.slots > 0 && g->main_ws.lcap == lcap && g->main_ws.xcap == xcap &&
-            g->main_ws.slots <= slots)
+            (g->main_ws.slots <= slots || max_slots > 0))
             slots = g->main_ws.slots;  // keep a working allocation
     }
     int rc = alloc_ws(g, g->main_ws, slots, lcap, xcap);
@@ -154,6 +178,12 @@ int prepare_workspaces(imin_graph *g)
         free_ws(g->big_ws);
     }
     return IMIN_OK;
+}
+
+int prepare_workspaces(imin_graph *g)
+{
+    reset_stale(g);
+    return size_workspaces(g, 0);
 }
 
 // Keep every slot's 32-bit epoch from wrapping: a launch of theta samples raises any slot's
@@ -184,6 +214,38 @@ int ensure_ovf(imin_graph *g, uint32_t theta)
     }
     g->ovf_cap = theta;
     return IMIN_OK;
+}
+
+int ensure_sj(imin_graph *g, uint32_t theta)
+{
+    if (theta <= g->sj_cap) return IMIN_OK;
+    dfree(g->d_sj);
+    if (!ok(hipMalloc(&g->d_sj, (size_t)theta * sizeof(uint32_t)))) {
+        g->sj_cap = 0;
+        return IMIN_ENOMEM;
+    }
+    g->sj_cap = theta;
+    return IMIN_OK;
+}
+
+bool small_enabled(const imin_graph *g)
+{
+    if (g->small_mode == 0) return false;
+    if (g->small_mode == 1) return true;
+    return !g->small_auto_off;
+}
+
+int small_grid(const imin_graph *g)
+{
+    const int32_t wpc = g->small_waves_per_cu > 0 ? g->small_waves_per_cu
+                                                  : kDefaultSmallWavesPerCu;
+    const int per_cu = std::max(1, (wpc + imin::kSmallWaves - 1) / imin::kSmallWaves);
+    return g->num_cus * per_cu;
+}
+
+int32_t quad_limit(const imin_graph *g)
+{
+    return g->quad_limit > 0 ? g->quad_limit : kDefaultQuadLimit;
 }
 
 int ensure_B(imin_graph *g, int32_t b)
@@ -218,15 +280,34 @@ int seed_setup(imin_graph *g, const int32_t *S, int32_t nS, std::vector<int32_t>
 }
 
 int upload_call_state(imin_graph *g, const std::vector<int32_t> &seeds,
-                      const std::vector<uint32_t> &inelig)
+                      const std::vector<uint32_t> &inelig, uint64_t seed, uint32_t theta)
 {
     if (!ok(hipMemcpyAsync(g->d_seeds, seeds.data(), seeds.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, g->stream)) ||
         !ok(hipMemcpyAsync(g->d_inelig, inelig.data(), inelig.size() * sizeof(uint32_t),
                            hipMemcpyHostToDevice, g->stream)))
         return IMIN_EDEVICE;
-    if (!ok(imin::launch_fill_u64(g->d_stats, 5, 0, g->stream)) ||
+    if (!ok(imin::launch_fill_u64(g->d_stats, kStats, 0, g->stream)) ||
         !ok(imin::launch_fill_u32(g->d_ctrl, 4, 0, g->stream)))
+        return IMIN_EDEVICE;
+    imin::InstanceDesc &I = g->h_inst;
+    I.row_ptr = g->d_row_ptr;
+    I.col4 = g->d_col4;
+    I.thr4 = g->d_thr4;
+    I.inelig = g->d_inelig;
+    I.seeds = g->d_seeds;
+    I.D = g->d_D;
+    I.stats = g->d_stats;
+    I.B = g->d_B;
+    I.x = g->d_x;
+    I.nseeds = (int32_t)seeds.size();
+    I.n = g->n;
+    I.seed_lo = (uint32_t)seed;
+    I.seed_hi = (uint32_t)(seed >> 32);
+    I.theta = theta;
+    I.sample_base = 0;
+    if (!ok(hipMemcpyAsync(g->d_inst, &g->h_inst, sizeof(imin::InstanceDesc),
+                           hipMemcpyHostToDevice, g->stream)))
         return IMIN_EDEVICE;
     // Slot-map stamps: clear the previous call's seeds and blockers, stamp the new ones.
     Workspace *wss[2] = {&g->main_ws, &g->big_ws};
@@ -274,8 +355,11 @@ int kernel_events(imin_graph *g, hipEvent_t *a, hipEvent_t *b)
     return IMIN_OK;
 }
 
-// One call of Algorithm 2 with Philox key `key`, leaving D on the device.
-int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key)
+// The workgroup-per-sample kernel with Philox key `key` over samples 0..theta-1, or over
+// the device list `list` of *count samples (at most theta), then the large-scratch launch
+// for the samples that overflowed it. D and the stats accumulate.
+int launch_large(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key,
+                 const uint32_t *list, const uint32_t *count)
 {
     int rc = guard_epochs(g, g->main_ws, theta);
     if (rc) return rc;
@@ -284,9 +368,7 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key)
         rc = guard_epochs(g, g->big_ws, theta);
         if (rc) return rc;
     }
-    if (!ok(imin::launch_fill_u64(g->d_D, g->n, 0, g->stream)) ||
-        !ok(imin::launch_fill_u32(g->d_ctrl, 3, 0, g->stream)))
-        return IMIN_EDEVICE;
+    if (!ok(imin::launch_fill_u32(g->d_ctrl, 3, 0, g->stream))) return IMIN_EDEVICE;
     DecreaseArgs a;
     std::memset(&a, 0, sizeof(a));
     a.row_ptr = g->d_row_ptr;
@@ -298,8 +380,8 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key)
     a.key_lo = (uint32_t)key;
     a.key_hi = (uint32_t)(key >> 32);
     a.theta = theta;
-    a.sample_list = nullptr;
-    a.sample_count = nullptr;
+    a.sample_list = list;
+    a.sample_count = count;
     a.next = g->d_ctrl + 0;
     a.D = g->d_D;
     a.stats = g->d_stats;
@@ -309,10 +391,6 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key)
     a.spill_ok = spill ? 1 : 0;
     a.ws = g->main_ws;
     a.ws.slots = (int32_t)std::min<uint32_t>((uint32_t)g->main_ws.slots, theta);
-    hipEvent_t k0, k1;
-    rc = kernel_events(g, &k0, &k1);
-    if (rc) return rc;
-    if (!ok(hipEventRecord(k0, g->stream))) return IMIN_EDEVICE;
     if (!ok(imin::launch_decrease(a, g->stream))) return IMIN_EDEVICE;
     if (spill) {
         a.sample_list = g->d_ovf;
@@ -322,6 +400,41 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key)
         a.ws = g->big_ws;
         if (!ok(imin::launch_decrease(a, g->stream))) return IMIN_EDEVICE;
     }
+    return IMIN_OK;
+}
+
+// One call of Algorithm 2 with Philox key seed + call, leaving D on the device. With the
+// wave kernel on, it runs every sample first and leaves the ones that outgrow it to the
+// workgroup kernel, through a device-side list (no host round trip).
+int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed, uint32_t call)
+{
+    const bool small = small_enabled(g);
+    if (!ok(imin::launch_fill_u64(g->d_D, g->n, 0, g->stream)) ||
+        (small && !ok(imin::launch_fill_u32(g->d_sctrl, 2, 0, g->stream))))
+        return IMIN_EDEVICE;
+    hipEvent_t k0, k1;
+    int rc = kernel_events(g, &k0, &k1);
+    if (rc) return rc;
+    if (!ok(hipEventRecord(k0, g->stream))) return IMIN_EDEVICE;
+    if (small) {
+        imin::SmallArgs s;
+        std::memset(&s, 0, sizeof(s));
+        s.inst = g->d_inst;
+        s.ninst = 1;
+        s.total = theta;
+        s.round = call;
+        s.quad_limit = quad_limit(g);
+        s.next = g->d_sctrl + 0;
+        s.spill_inst = nullptr;
+        s.spill_j = g->d_sj;
+        s.spill_count = g->d_sctrl + 1;
+        s.error = g->d_ctrl + 3;
+        if (!ok(imin::launch_decrease_small(s, small_grid(g), g->stream))) return IMIN_EDEVICE;
+        rc = launch_large(g, nseeds, theta, seed + call, g->d_sj, g->d_sctrl + 1);
+    } else {
+        rc = launch_large(g, nseeds, theta, seed + call, nullptr, nullptr);
+    }
+    if (rc) return rc;
     if (!ok(hipEventRecord(k1, g->stream))) return IMIN_EDEVICE;
     return IMIN_OK;
 }
@@ -329,7 +442,7 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key)
 // Copies the stats and the error flag back; returns IMIN_EDEVICE if a sample was lost.
 int finish_call(imin_graph *g, imin_stats *stats)
 {
-    unsigned long long st[5];
+    unsigned long long st[kStats];
     uint32_t ctrl[4];
     if (!ok(hipMemcpyAsync(st, g->d_stats, sizeof(st), hipMemcpyDeviceToHost, g->stream)) ||
         !ok(hipMemcpyAsync(ctrl, g->d_ctrl, sizeof(ctrl), hipMemcpyDeviceToHost, g->stream)) ||
@@ -344,6 +457,7 @@ int finish_call(imin_graph *g, imin_stats *stats)
         stats->edges_scanned = st[2];
         stats->live_edges = st[3];
         stats->spilled = st[4];
+        stats->wave_samples = st[5];
         stats->device_ms = ms;
         double kms = 0.0;
         for (size_t i = 0; i + 1 < g->kev_used; i += 2) {
@@ -353,6 +467,19 @@ int finish_call(imin_graph *g, imin_stats *stats)
         }
         stats->kernel_ms = kms;
     }
+    return IMIN_OK;
+}
+
+// Automatic wave-kernel policy: after a graph's first round with the wave kernel on, keep
+// it only if it finished most of the samples (the results are the same either way).
+int auto_check(imin_graph *g)
+{
+    if (g->small_mode != -1 || g->small_auto_off) return IMIN_OK;
+    unsigned long long st[kStats];
+    if (!ok(hipMemcpyAsync(st, g->d_stats, sizeof(st), hipMemcpyDeviceToHost, g->stream)) ||
+        !ok(hipStreamSynchronize(g->stream)))
+        return IMIN_EDEVICE;
+    if ((double)st[5] < kSmallKeepShare * (double)st[0]) g->small_auto_off = true;
     return IMIN_OK;
 }
 
@@ -381,6 +508,9 @@ void destroy(imin_graph *g)
     dfree(g->d_D);
     dfree(g->d_stats);
     dfree(g->d_ctrl);
+    dfree(g->d_sctrl);
+    dfree(g->d_sj);
+    dfree(g->d_inst);
     dfree(g->d_ovf);
     dfree(g->d_part_d);
     dfree(g->d_part_i);
@@ -391,6 +521,55 @@ void destroy(imin_graph *g)
     if (g->ev1) (void)hipEventDestroy(g->ev1);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
+}
+
+// Workgroup-kernel slots given to a graph whose samples first outgrow the wave kernel
+// inside a batched call (a graph that already has scratch keeps it).
+constexpr int32_t kBatchSlots = 64;
+
+// A batched call runs every graph's work on one stream; each graph's own stream is put back
+// when the call ends, however it ends.
+struct StreamSwap {
+    std::vector<std::pair<imin_graph *, hipStream_t>> saved;
+    void use(imin_graph *g, hipStream_t s)
+    {
+        saved.emplace_back(g, g->stream);
+        g->stream = s;
+    }
+    ~StreamSwap()
+    {
+        for (auto &p : saved) p.first->stream = p.second;
+    }
+};
+
+template <class T>
+struct DeviceBuf {
+    T *p = nullptr;
+    ~DeviceBuf() { dfree(p); }
+    bool alloc(size_t count) { return ok(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T))); }
+};
+
+struct BatchItem {
+    imin_instance *in = nullptr;
+    imin_graph *g = nullptr;
+    std::vector<int32_t> seeds;
+    std::vector<uint32_t> inelig;
+    int32_t rounds = 0;
+};
+
+// Scratch for a graph's first spilled samples of a batched call. The new slot maps start
+// from the seed/blocked bitmap as it stands on the device, blockers of earlier rounds
+// included.
+int batch_workspace(imin_graph *g)
+{
+    if (g->main_ws.slots > 0) return IMIN_OK;
+    int rc = size_workspaces(g, kBatchSlots);
+    if (rc) return rc;
+    Workspace *wss[2] = {&g->main_ws, &g->big_ws};
+    for (Workspace *ws : wss)
+        if (!ok(imin::launch_mark_bitmap(ws->map, ws->slots, g->n, g->d_inelig, g->stream)))
+            return IMIN_EDEVICE;
+    return IMIN_OK;
 }
 
 }  // namespace
@@ -471,8 +650,10 @@ int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
         ok(hipMalloc(&g->d_seeds, (size_t)n * sizeof(int32_t))) &&
         ok(hipMalloc(&g->d_list, (size_t)n * sizeof(int32_t))) &&
         ok(hipMalloc(&g->d_D, (size_t)n * sizeof(unsigned long long))) &&
-        ok(hipMalloc(&g->d_stats, 5 * sizeof(unsigned long long))) &&
+        ok(hipMalloc(&g->d_stats, kStats * sizeof(unsigned long long))) &&
         ok(hipMalloc(&g->d_ctrl, 4 * sizeof(uint32_t))) &&
+        ok(hipMalloc(&g->d_sctrl, 2 * sizeof(uint32_t))) &&
+        ok(hipMalloc(&g->d_inst, sizeof(imin::InstanceDesc))) &&
         ok(hipMalloc(&g->d_part_d, (size_t)g->parts * sizeof(unsigned long long))) &&
         ok(hipMalloc(&g->d_part_i, (size_t)g->parts * sizeof(int32_t))) &&
         ok(hipMalloc(&g->d_x, sizeof(int32_t)));
@@ -527,9 +708,12 @@ int imin_decrease(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *bl
     if (rc) return rc;
     rc = ensure_ovf(g, theta);
     if (rc) return rc;
-    rc = upload_call_state(g, seeds, inelig);
+    rc = ensure_sj(g, theta);
     if (rc) return rc;
-    rc = decrease_round(g, (int32_t)seeds.size(), theta, seed);
+    rc = upload_call_state(g, seeds, inelig, seed, theta);
+    if (rc) return rc;
+    const bool small = small_enabled(g);
+    rc = decrease_round(g, (int32_t)seeds.size(), theta, seed, 0);
     if (rc) return rc;
     std::vector<unsigned long long> D((size_t)g->n);
     if (!ok(hipMemcpyAsync(D.data(), g->d_D, (size_t)g->n * sizeof(unsigned long long),
@@ -539,6 +723,9 @@ int imin_decrease(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *bl
     rc = finish_call(g, &st);
     if (rc) return rc;
     g->marks_valid = true;
+    if (small && g->small_mode == -1 &&
+        (double)st.wave_samples < kSmallKeepShare * (double)st.samples)
+        g->small_auto_off = true;
     std::memcpy(counts, D.data(), (size_t)g->n * sizeof(uint64_t));
     if (stats) *stats = st;
     return IMIN_OK;
@@ -562,9 +749,11 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
     if (rc) return rc;
     rc = ensure_ovf(g, theta);
     if (rc) return rc;
+    rc = ensure_sj(g, theta);
+    if (rc) return rc;
     rc = ensure_B(g, b);
     if (rc) return rc;
-    rc = upload_call_state(g, seeds, inelig);
+    rc = upload_call_state(g, seeds, inelig, seed, theta);
     if (rc) return rc;
 
     std::vector<int32_t> B;
@@ -572,8 +761,12 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
     if (mode == IMIN_AG) {
         const int32_t rounds = std::min<int32_t>(b, g->n - ns);
         for (int32_t r = 0; r < rounds; ++r) {
-            rc = decrease_round(g, ns, theta, seed + call);
+            rc = decrease_round(g, ns, theta, seed, call);
             if (rc) return rc;
+            if (call == 0) {
+                rc = auto_check(g);
+                if (rc) return rc;
+            }
             ++call;
             if (!ok(imin::launch_argmax_apply(g->d_D, g->d_inelig, 0, g->n, g->d_part_d,
                                               g->d_part_i, g->parts, g->d_inelig, nullptr,
@@ -606,8 +799,12 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
             return IMIN_EDEVICE;
         const int32_t k = std::min(ncb, b);
         for (int32_t r = 0; r < k; ++r) {
-            rc = decrease_round(g, ns, theta, seed + call);
+            rc = decrease_round(g, ns, theta, seed, call);
             if (rc) return rc;
+            if (call == 0) {
+                rc = auto_check(g);
+                if (rc) return rc;
+            }
             ++call;
             if (!ok(imin::launch_argmax_apply(g->d_D, g->d_cand, 1, g->n, g->d_part_d,
                                               g->d_part_i, g->parts, g->d_inelig, g->d_cand,
@@ -633,8 +830,12 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
             if (!ok(imin::launch_set_bit(g->d_inelig, u, 0, g->stream))) return IMIN_EDEVICE;
             rc = stamp_vertex(g, u, nullptr, 0u);
             if (rc) return rc;
-            rc = decrease_round(g, ns, theta, seed + call);
+            rc = decrease_round(g, ns, theta, seed, call);
             if (rc) return rc;
+            if (call == 0) {
+                rc = auto_check(g);
+                if (rc) return rc;
+            }
             ++call;
             if (!ok(imin::launch_argmax_apply(g->d_D, g->d_inelig, 0, g->n, g->d_part_d,
                                               g->d_part_i, g->parts, g->d_inelig, nullptr,
@@ -663,6 +864,212 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
     std::copy(B.begin(), B.end(), blockers);
     *n_blockers = (int32_t)B.size();
     if (stats) *stats = st;
+    return IMIN_OK;
+}
+
+int imin_set_small(imin_graph *g, int32_t enable, int32_t waves_per_cu, int32_t quad_limit)
+{
+    if (!g || enable < -1 || enable > 1 || waves_per_cu < 0 || quad_limit < 0) return IMIN_EINVAL;
+    g->small_mode = enable;
+    g->small_auto_off = false;
+    g->small_waves_per_cu = waves_per_cu;
+    g->quad_limit = quad_limit;
+    return IMIN_OK;
+}
+
+int imin_greedy_batch(imin_instance *inst, int32_t count, int mode)
+{
+    if (!inst || count <= 0 || mode != IMIN_AG) return IMIN_EINVAL;
+    std::vector<BatchItem> items((size_t)count);
+    std::vector<imin_graph *> graphs;
+    uint64_t theta_sum = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        imin_instance &in = inst[i];
+        if (!in.g || in.theta == 0 || in.b < 0 || !in.n_blockers || (in.b > 0 && !in.blockers))
+            return IMIN_EINVAL;
+        if (in.g->device != inst[0].g->device) return IMIN_EINVAL;
+        BatchItem &it = items[(size_t)i];
+        it.in = &in;
+        it.g = in.g;
+        int rc = seed_setup(in.g, in.S, in.nS, it.seeds, it.inelig);
+        if (rc) return rc;
+        it.rounds = std::min<int32_t>(in.b, in.g->n - (int32_t)it.seeds.size());
+        theta_sum += in.theta;
+        graphs.push_back(in.g);
+    }
+    std::sort(graphs.begin(), graphs.end());
+    if (std::adjacent_find(graphs.begin(), graphs.end()) != graphs.end()) return IMIN_EINVAL;
+    if (theta_sum > kMaxTheta) return IMIN_ERANGE;
+    // Instances with more rounds first: the ones still active in round r form a prefix.
+    std::stable_sort(items.begin(), items.end(),
+                     [](const BatchItem &a, const BatchItem &b) { return a.rounds > b.rounds; });
+    if (!ok(hipSetDevice(inst[0].g->device))) return IMIN_EDEVICE;
+    for (imin_graph *g : graphs)
+        if (!ok(hipStreamSynchronize(g->stream))) return IMIN_EDEVICE;
+    const hipStream_t bs = inst[0].g->stream;
+    StreamSwap swap;
+    for (imin_graph *g : graphs) swap.use(g, bs);
+
+    imin_graph *g0 = inst[0].g;
+    g0->kev_used = 0;
+    if (!ok(hipEventRecord(g0->ev0, bs))) return IMIN_EDEVICE;
+    std::vector<imin::InstanceDesc> table((size_t)count);
+    std::vector<uint32_t> prefix((size_t)count + 1, 0u);
+    int32_t max_rounds = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        BatchItem &it = items[(size_t)i];
+        imin_graph *g = it.g;
+        reset_stale(g);
+        int rc = ensure_ovf(g, it.in->theta);
+        if (rc) return rc;
+        rc = ensure_sj(g, it.in->theta);
+        if (rc) return rc;
+        rc = ensure_B(g, it.rounds);
+        if (rc) return rc;
+        rc = upload_call_state(g, it.seeds, it.inelig, it.in->seed, it.in->theta);
+        if (rc) return rc;
+        table[(size_t)i] = g->h_inst;
+        table[(size_t)i].sample_base = prefix[(size_t)i];
+        prefix[(size_t)i + 1] = prefix[(size_t)i] + it.in->theta;
+        max_rounds = std::max(max_rounds, it.rounds);
+    }
+    DeviceBuf<imin::InstanceDesc> d_table;
+    DeviceBuf<uint32_t> d_si, d_sj, d_ctrl;
+    if (!d_table.alloc((size_t)count) || !d_si.alloc(theta_sum) || !d_sj.alloc(theta_sum) ||
+        !d_ctrl.alloc(3)) {
+        (void)hipGetLastError();
+        return IMIN_ENOMEM;
+    }
+    if (!ok(hipMemcpyAsync(d_table.p, table.data(), table.size() * sizeof(imin::InstanceDesc),
+                           hipMemcpyHostToDevice, bs)) ||
+        !ok(imin::launch_fill_u32(d_ctrl.p, 3, 0, bs)))
+        return IMIN_EDEVICE;
+    int rc = IMIN_OK;
+    int32_t active = count;
+    std::vector<uint32_t> spill_i, spill_j, counts((size_t)count, 0u);
+    std::vector<std::vector<uint32_t>> lists((size_t)count);
+    for (int32_t r = 0; r < max_rounds; ++r) {
+        while (active > 0 && items[(size_t)active - 1].rounds <= r) --active;
+        hipEvent_t k0, k1;
+        rc = kernel_events(g0, &k0, &k1);
+        if (rc) return rc;
+        if (!ok(imin::launch_batch_zero(d_table.p, active, bs)) ||
+            !ok(imin::launch_fill_u32(d_ctrl.p, 2, 0, bs)) || !ok(hipEventRecord(k0, bs)))
+            return IMIN_EDEVICE;
+        imin::SmallArgs s;
+        std::memset(&s, 0, sizeof(s));
+        s.inst = d_table.p;
+        s.ninst = active;
+        s.total = prefix[(size_t)active];
+        s.round = (uint32_t)r;
+        s.quad_limit = quad_limit(g0);
+        s.next = d_ctrl.p + 0;
+        s.spill_inst = d_si.p;
+        s.spill_j = d_sj.p;
+        s.spill_count = d_ctrl.p + 1;
+        s.error = d_ctrl.p + 2;
+        if (!ok(imin::launch_decrease_small(s, small_grid(g0), bs))) return IMIN_EDEVICE;
+        uint32_t nspill = 0;
+        if (!ok(hipMemcpyAsync(&nspill, d_ctrl.p + 1, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               bs)) ||
+            !ok(hipStreamSynchronize(bs)))
+            return IMIN_EDEVICE;
+        if (nspill > 0) {
+            spill_i.resize(nspill);
+            spill_j.resize(nspill);
+            if (!ok(hipMemcpyAsync(spill_i.data(), d_si.p, nspill * sizeof(uint32_t),
+                                   hipMemcpyDeviceToHost, bs)) ||
+                !ok(hipMemcpyAsync(spill_j.data(), d_sj.p, nspill * sizeof(uint32_t),
+                                   hipMemcpyDeviceToHost, bs)) ||
+                !ok(hipStreamSynchronize(bs)))
+                return IMIN_EDEVICE;
+            for (auto &l : lists) l.clear();
+            for (uint32_t k = 0; k < nspill; ++k) {
+                if (spill_i[k] >= (uint32_t)active) return IMIN_EDEVICE;
+                lists[spill_i[k]].push_back(spill_j[k]);
+            }
+            for (int32_t i = 0; i < active; ++i) {
+                std::vector<uint32_t> &l = lists[(size_t)i];
+                if (l.empty()) continue;
+                BatchItem &it = items[(size_t)i];
+                imin_graph *g = it.g;
+                rc = batch_workspace(g);
+                if (rc) return rc;
+                counts[(size_t)i] = (uint32_t)l.size();
+                // The wave kernel left these samples untouched. The host lists and counts
+                // stay alive until the wait of the next round.
+                if (!ok(hipMemcpyAsync(g->d_sj, l.data(), l.size() * sizeof(uint32_t),
+                                       hipMemcpyHostToDevice, bs)) ||
+                    !ok(hipMemcpyAsync(g->d_sctrl + 1, &counts[(size_t)i], sizeof(uint32_t),
+                                       hipMemcpyHostToDevice, bs)))
+                    return IMIN_EDEVICE;
+                rc = launch_large(g, (int32_t)it.seeds.size(), it.in->theta,
+                                  it.in->seed + (uint64_t)r, g->d_sj, g->d_sctrl + 1);
+                if (rc) return rc;
+            }
+        }
+        if (!ok(hipEventRecord(k1, bs)) || !ok(imin::launch_batch_argmax(d_table.p, active, r, bs)))
+            return IMIN_EDEVICE;
+        for (int32_t i = 0; i < active; ++i) {
+            imin_graph *g = items[(size_t)i].g;
+            if (g->main_ws.slots > 0) {
+                rc = stamp_vertex(g, 0, g->d_x, imin::kInelig);
+                if (rc) return rc;
+            }
+        }
+    }
+    // Results: every graph's blocker slots, counters and error flag, then one wait.
+    std::vector<std::vector<int32_t>> B((size_t)count);
+    std::vector<std::array<unsigned long long, kStats>> st((size_t)count);
+    std::vector<std::array<uint32_t, 4>> ctrl((size_t)count);
+    uint32_t berr[3] = {0, 0, 0};
+    for (int32_t i = 0; i < count; ++i) {
+        BatchItem &it = items[(size_t)i];
+        B[(size_t)i].assign((size_t)it.rounds, -1);
+        if ((it.rounds > 0 &&
+             !ok(hipMemcpyAsync(B[(size_t)i].data(), it.g->d_B, (size_t)it.rounds * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, bs))) ||
+            !ok(hipMemcpyAsync(st[(size_t)i].data(), it.g->d_stats,
+                               kStats * sizeof(unsigned long long), hipMemcpyDeviceToHost, bs)) ||
+            !ok(hipMemcpyAsync(ctrl[(size_t)i].data(), it.g->d_ctrl, 4 * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, bs)))
+            return IMIN_EDEVICE;
+    }
+    if (!ok(hipMemcpyAsync(berr, d_ctrl.p, sizeof(berr), hipMemcpyDeviceToHost, bs)) ||
+        !ok(hipEventRecord(g0->ev1, bs)) || !ok(hipEventSynchronize(g0->ev1)))
+        return IMIN_EDEVICE;
+    if (berr[2] != 0) return IMIN_EDEVICE;
+    float total_ms = 0.0f;
+    if (!ok(hipEventElapsedTime(&total_ms, g0->ev0, g0->ev1))) return IMIN_EDEVICE;
+    double kms = 0.0;
+    for (size_t k = 0; k + 1 < g0->kev_used; k += 2) {
+        float x = 0.0f;
+        if (!ok(hipEventElapsedTime(&x, g0->kev[k], g0->kev[k + 1]))) return IMIN_EDEVICE;
+        kms += x;
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        if (ctrl[(size_t)i][3] != 0) return IMIN_EDEVICE;
+        for (int32_t v : B[(size_t)i])
+            if (v < 0) return IMIN_EDEVICE;
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        BatchItem &it = items[(size_t)i];
+        for (int32_t v : B[(size_t)i]) it.g->marked.push_back(v);
+        it.g->marks_valid = true;
+        std::copy(B[(size_t)i].begin(), B[(size_t)i].end(), it.in->blockers);
+        *it.in->n_blockers = it.rounds;
+        if (it.in->stats) {
+            imin_stats &o = *it.in->stats;
+            o.samples = st[(size_t)i][0];
+            o.reached = st[(size_t)i][1];
+            o.edges_scanned = st[(size_t)i][2];
+            o.live_edges = st[(size_t)i][3];
+            o.spilled = st[(size_t)i][4];
+            o.wave_samples = st[(size_t)i][5];
+            o.device_ms = total_ms;
+            o.kernel_ms = kms;
+        }
+    }
     return IMIN_OK;
 }
 

@@ -25,35 +25,10 @@
 // A sample whose scratch overflows is recorded and re-run by a second launch with
 // large-capacity slots; its partial work is discarded, so results never depend on that.
 #include "imin_internal.h"
+#include "philox.h"
 
 namespace imin {
 namespace {
-
-__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t k0, uint32_t k1,
-                                              uint32_t &r0, uint32_t &r1, uint32_t &r2,
-                                              uint32_t &r3)
-{
-    // Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as easy as 1, 2, 3" (SC'11).
-    // Counter words 2 and 3 are zero here.
-    uint32_t x0 = c0, x1 = c1, x2 = 0u, x3 = 0u;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * x0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, x0);
-        const uint32_t lo1 = 0xCD9E8D57u * x2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, x2);
-        x0 = hi1 ^ x1 ^ k0;
-        x1 = lo1;
-        x2 = hi0 ^ x3 ^ k1;
-        x3 = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    r0 = x0;
-    r1 = x1;
-    r2 = x2;
-    r3 = x3;
-}
 
 // Exclusive prefix sum over the workgroup; *total receives the sum of all values.
 __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *total)
@@ -149,22 +124,6 @@ __device__ __forceinline__ void locate(const Shared &sh, int cnt, int q, int &l,
     quad = (sh.e0[lo] >> 2) + (q - sh.qpre[lo]);
 }
 
-// Live-edge bits of one quad for sample j: bit i set when edge 4*quad+i lies in [e0, e1)
-// and its coin falls under its threshold.
-__device__ __forceinline__ uint32_t quad_mask(const DecreaseArgs &a, int quad, uint32_t j, int e0,
-                                              int e1, uint4 thr)
-{
-    uint32_t w0, w1, w2, w3;
-    philox4x32_10((uint32_t)quad, j, a.key_lo, a.key_hi, w0, w1, w2, w3);
-    const int eb = quad * 4;
-    uint32_t mask = 0;
-    mask |= (eb + 0 >= e0 && eb + 0 < e1 && (w0 >> 8) < thr.x) ? 1u : 0u;
-    mask |= (eb + 1 >= e0 && eb + 1 < e1 && (w1 >> 8) < thr.y) ? 2u : 0u;
-    mask |= (eb + 2 >= e0 && eb + 2 < e1 && (w2 >> 8) < thr.z) ? 4u : 0u;
-    mask |= (eb + 3 >= e0 && eb + 3 < e1 && (w3 >> 8) < thr.w) ? 8u : 0u;
-    return mask;
-}
-
 __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView &sv, Shared &sh,
                                            uint32_t mask, uint4 col, int src, uint32_t epoch,
                                            uint32_t &live)
@@ -223,8 +182,8 @@ __device__ void expand(const DecreaseArgs &a, const SlotView &sv, Shared &sh, bo
             locate(sh, cnt, has2 ? q2 : q, l2, quad2);
             const uint4 t1 = a.thr4[quad1];
             const uint4 t2 = a.thr4[quad2];
-            const uint32_t m1 = quad_mask(a, quad1, j, sh.e0[l1], sh.e1[l1], t1);
-            const uint32_t m2 = has2 ? quad_mask(a, quad2, j, sh.e0[l2], sh.e1[l2], t2) : 0u;
+            const uint32_t m1 = live_mask(quad1, j, a.key_lo, a.key_hi, sh.e0[l1], sh.e1[l1], t1);
+            const uint32_t m2 = has2 ? live_mask(quad2, j, a.key_lo, a.key_hi, sh.e0[l2], sh.e1[l2], t2) : 0u;
             uint4 c1 = make_uint4(0, 0, 0, 0), c2 = make_uint4(0, 0, 0, 0);
             if (m1) c1 = a.col4[quad1];
             if (m2) c2 = a.col4[quad2];

@@ -68,6 +68,48 @@ struct DecreaseArgs {
 // decrease.hip
 hipError_t launch_decrease(const DecreaseArgs &a, hipStream_t stream);
 
+// Wave-per-sample kernel (small.hip): per-sample capacity in local vertices (root
+// included) and in non-tree live edges, and waves per workgroup.
+constexpr int kSmallV = 256;
+constexpr int kSmallX = 256;
+constexpr int kSmallWaves = 4;
+
+// One problem instance of a wave-kernel launch: a resident graph, its seed set and
+// seed/blocked bitmap, and its counters. Samples [sample_base, sample_base + theta) of the
+// launch belong to it; sample j of the instance uses Philox key seed + round.
+struct InstanceDesc {
+    const int32_t *row_ptr;
+    const uint4 *col4;
+    const uint4 *thr4;
+    uint32_t *inelig;         // bit v set: v is a seed or blocked (the argmax adds winners)
+    const int32_t *seeds;
+    unsigned long long *D;    // n decrease counters
+    unsigned long long *stats; // samples, reached, edges scanned, live edges, -, wave samples
+    int32_t *B;               // blocker slots (batched greedy)
+    int32_t *x;               // the last round's winner (batched greedy)
+    int32_t nseeds;
+    int32_t n;
+    uint32_t seed_lo, seed_hi;
+    uint32_t theta;
+    uint32_t sample_base;
+};
+
+struct SmallArgs {
+    const InstanceDesc *inst; // ascending sample_base
+    int32_t ninst;
+    uint32_t total;           // samples of the launch: sum of the instances' theta
+    uint32_t round;           // added to every instance's seed to form the key
+    int32_t quad_limit;       // a frontier chunk with more edge quads goes to the large kernel
+    uint32_t *next;           // work counter
+    uint32_t *spill_inst;     // samples left to the large kernel: instance, sample index
+    uint32_t *spill_j;
+    uint32_t *spill_count;
+    uint32_t *error;          // bit 2: dominator iteration did not settle (never expected)
+};
+
+// small.hip
+hipError_t launch_decrease_small(const SmallArgs &a, int grid, hipStream_t stream);
+
 // select.hip
 hipError_t launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long value,
                            hipStream_t stream);
@@ -89,5 +131,11 @@ hipError_t launch_set_stamps(SlotEntry *map, int32_t slots, int32_t n, const int
                              int32_t count, uint32_t value, hipStream_t stream);
 hipError_t launch_set_stamp(SlotEntry *map, int32_t slots, int32_t n, int32_t v,
                             const int32_t *v_dev, uint32_t value, hipStream_t stream);
+// Batched greedy over instances inst[0..ninst): zero every instance's D; and per instance,
+// the AdvancedGreedy selection (argmax of D over vertices whose inelig bit is clear, ties to
+// the smallest id), applied as launch_argmax_apply does, with the winner in B[slot] and *x.
+hipError_t launch_batch_zero(const InstanceDesc *inst, int32_t ninst, hipStream_t stream);
+hipError_t launch_batch_argmax(const InstanceDesc *inst, int32_t ninst, int32_t slot,
+                               hipStream_t stream);
 
 }  // namespace imin

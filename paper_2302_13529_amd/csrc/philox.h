@@ -1,0 +1,51 @@
+// philox.h -- Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as easy
+// as 1, 2, 3", SC'11) for the live-edge coins of the GPU kernels. Counter words 2 and 3 are
+// always zero here: the counter is (edge quad, sample index, 0, 0).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace imin {
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t k0, uint32_t k1,
+                                              uint32_t &r0, uint32_t &r1, uint32_t &r2,
+                                              uint32_t &r3)
+{
+    uint32_t x0 = c0, x1 = c1, x2 = 0u, x3 = 0u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * x0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, x0);
+        const uint32_t lo1 = 0xCD9E8D57u * x2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, x2);
+        x0 = hi1 ^ x1 ^ k0;
+        x1 = lo1;
+        x2 = hi0 ^ x3 ^ k1;
+        x3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    r0 = x0;
+    r1 = x1;
+    r2 = x2;
+    r3 = x3;
+}
+
+// Live-edge bits of one quad of 4 edges for sample j: bit i is set when edge 4*quad+i lies in
+// [e0, e1) and its 24-bit coin falls under its threshold ceil(p * 2^24).
+__device__ __forceinline__ uint32_t live_mask(int quad, uint32_t j, uint32_t key_lo,
+                                              uint32_t key_hi, int e0, int e1, uint4 thr)
+{
+    uint32_t w0, w1, w2, w3;
+    philox4x32_10((uint32_t)quad, j, key_lo, key_hi, w0, w1, w2, w3);
+    const int eb = quad * 4;
+    uint32_t mask = 0;
+    mask |= (eb + 0 >= e0 && eb + 0 < e1 && (w0 >> 8) < thr.x) ? 1u : 0u;
+    mask |= (eb + 1 >= e0 && eb + 1 < e1 && (w1 >> 8) < thr.y) ? 2u : 0u;
+    mask |= (eb + 2 >= e0 && eb + 2 < e1 && (w2 >> 8) < thr.z) ? 4u : 0u;
+    mask |= (eb + 3 >= e0 && eb + 3 < e1 && (w3 >> 8) < thr.w) ? 8u : 0u;
+    return mask;
+}
+
+}  // namespace imin

@@ -129,6 +129,32 @@ __global__ void set_stamp_kernel(SlotEntry *map, int32_t slots, int32_t n, int32
         map[(size_t)s * n + x].stamp = value;
 }
 
+__global__ void batch_zero_kernel(const InstanceDesc *inst)
+{
+    const InstanceDesc &I = inst[blockIdx.y];
+    for (int64_t v = blockIdx.x * (int64_t)kSelBlock + threadIdx.x; v < I.n;
+         v += (int64_t)gridDim.x * kSelBlock)
+        I.D[v] = 0ull;
+}
+
+// One workgroup per instance.
+__global__ void batch_argmax_kernel(const InstanceDesc *inst, int32_t slot)
+{
+    const InstanceDesc &I = inst[blockIdx.x];
+    unsigned long long bd = 0;
+    int bi = -1;
+    for (int32_t v = threadIdx.x; v < I.n; v += kSelBlock)
+        if (!((I.inelig[v >> 5] >> (v & 31)) & 1u)) better(bd, bi, I.D[v], (int)v);
+    block_best(bd, bi);
+    if (threadIdx.x == 0) {
+        if (bi >= 0) {
+            I.inelig[bi >> 5] |= 1u << (bi & 31);
+            I.B[slot] = bi;
+        }
+        *I.x = bi;
+    }
+}
+
 int grid_for(int64_t count)
 {
     int64_t g = (count + kSelBlock - 1) / kSelBlock;
@@ -202,6 +228,22 @@ hipError_t launch_set_stamp(SlotEntry *map, int32_t slots, int32_t n, int32_t v,
 hipError_t launch_set_bit(uint32_t *bits, int32_t v, int value, hipStream_t stream)
 {
     hipLaunchKernelGGL(set_bit_kernel, dim3(1), dim3(1), 0, stream, bits, v, value);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_batch_zero(const InstanceDesc *inst, int32_t ninst, hipStream_t stream)
+{
+    if (ninst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_zero_kernel, dim3(64, ninst), dim3(kSelBlock), 0, stream, inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_argmax(const InstanceDesc *inst, int32_t ninst, int32_t slot,
+                               hipStream_t stream)
+{
+    if (ninst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_argmax_kernel, dim3(ninst), dim3(kSelBlock), 0, stream, inst, slot);
     return hipGetLastError();
 }
 

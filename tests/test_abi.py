@@ -21,7 +21,7 @@ def declared_functions():
 def test_header_declares_the_api():
     names = set(declared_functions())
     assert {"imin_graph_create", "imin_graph_destroy", "imin_decrease", "imin_greedy",
-            "imin_set_launch", "imin_strerror"} <= names
+            "imin_greedy_batch", "imin_set_launch", "imin_set_small", "imin_strerror"} <= names
 
 
 def test_library_exports_every_declared_symbol():
@@ -76,4 +76,19 @@ def test_null_handle_is_rejected():
     assert lib.imin_decrease(None, S.ctypes.data_as(ctypes.c_void_p), 1, None, 10, 0,
                              D.ctypes.data_as(ctypes.c_void_p), None) == binding.IMIN_EINVAL
     assert lib.imin_set_launch(None, 1, 1) == binding.IMIN_EINVAL
+    assert lib.imin_set_small(None, 1, 0, 0) == binding.IMIN_EINVAL
+    assert lib.imin_greedy_batch(None, 1, 0) == binding.IMIN_EINVAL
     lib.imin_graph_destroy(None)
+
+
+def test_batch_rejects_null_graph_before_touching_a_device():
+    lib = binding.load()
+    arr = (binding.imin_instance * 1)()
+    S = np.array([0], np.int32)
+    arr[0].g = None
+    arr[0].S = S.ctypes.data_as(ctypes.c_void_p)
+    arr[0].nS = 1
+    arr[0].b = 1
+    arr[0].theta = 10
+    assert lib.imin_greedy_batch(arr, 1, 0) == binding.IMIN_EINVAL
+    assert lib.imin_greedy_batch(arr, 0, 0) == binding.IMIN_EINVAL

@@ -1,0 +1,169 @@
+"""The wave-per-sample kernel and the batched greedy call against the CPU oracle.
+
+Every sample first runs in one wavefront; the ones that outgrow it (more than 255 reached
+vertices, more than 256 non-tree live edges, or a heavy frontier chunk) are handed to the
+workgroup kernel. Counts and choices must not depend on which kernel finished a sample, so
+everything here is compared bit-exactly with the oracle and with the plain per-graph calls.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2302_13529_amd import graphgen as gg
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def batch16():
+    case("generating 16 batched Chung-Lu instances")
+    return gg.batched_instances(count=16, seed=3)
+
+
+def _path_graph(n=300):
+    return H.csr_from_edges(n, [(i, i + 1, 1.0) for i in range(n - 1)])
+
+
+def _dense_graph(k=40, seed=0):
+    rng = np.random.default_rng(seed)
+    edges = [(u, v, 1.0) for u in range(k) for v in range(k) if u != v and rng.random() < 0.6]
+    return H.csr_from_edges(k, edges)
+
+
+def test_wave_kernel_takes_small_samples_and_hands_over_large_ones(gpu):
+    tiny = gg.tiny_plain()
+    g = gpu.Graph(tiny.row_ptr, tiny.col, tiny.prob)
+    g.set_small(1)
+    case("tiny, wave kernel forced on")
+    D, st = g.decrease(tiny.seeds, None, 2000, 4)
+    Do, so = orc.decrease(tiny.n, tiny.row_ptr, tiny.col, tiny.prob, tiny.seeds, None, 2000, 4)
+    assert np.array_equal(D, Do)
+    assert st["wave_samples"] > 0
+    g.close()
+    # a certain path of 300 vertices reaches 299 vertices in every sample: all handed over
+    rp, c, p = _path_graph()
+    g = gpu.Graph(rp, c, p)
+    g.set_small(1)
+    case("path 300, every sample outgrows the wave kernel")
+    D, st = g.decrease([0], None, 50, 0)
+    Do, so = orc.decrease(300, rp, c, p, [0], None, 50, 0)
+    assert np.array_equal(D, Do) and st["wave_samples"] == 0
+    g.close()
+    # a path of 255 vertices: 254 reached plus the root fit exactly
+    rp, c, p = _path_graph(255)
+    g = gpu.Graph(rp, c, p)
+    g.set_small(1)
+    case("path 255, the largest sample the wave kernel keeps")
+    D, st = g.decrease([0], None, 50, 0)
+    Do, so = orc.decrease(255, rp, c, p, [0], None, 50, 0)
+    assert np.array_equal(D, Do) and st["wave_samples"] == 50
+    g.close()
+    # 40 certain vertices with ~900 non-tree live edges: the extra-edge list overflows
+    rp, c, p = _dense_graph()
+    g = gpu.Graph(rp, c, p)
+    g.set_small(1)
+    case("dense 40, extra-edge overflow")
+    D, st = g.decrease([0], None, 50, 0)
+    Do, so = orc.decrease(40, rp, c, p, [0], None, 50, 0)
+    assert np.array_equal(D, Do) and st["wave_samples"] == 0
+    g.close()
+
+
+def test_automatic_policy_keeps_results(gpu):
+    """The automatic mode may switch the wave kernel off after a round; the counts of later
+    calls stay identical."""
+    rp, c, p = _path_graph()
+    g = gpu.Graph(rp, c, p)
+    case("path 300 greedy, automatic wave-kernel policy")
+    B, st = g.greedy([0], 3, 40, 0, gpu.IMIN_AG)
+    Bo, calls, so = orc.greedy(300, rp, c, p, [0], 3, 40, 0, 0)
+    assert list(B) == list(Bo) and st["reached"] == so["reached"]
+    assert st["wave_samples"] == 0
+    g.close()
+
+
+def test_batch_equals_plain_and_oracle(gpu, batch16):
+    insts = batch16
+    graphs = [gpu.Graph(t.row_ptr, t.col, t.prob) for t in insts]
+    # budgets and sample counts differ per instance, including an empty budget
+    bs = [0, 1, 5, 3, 5, 2, 4, 5, 1, 5, 3, 5, 5, 2, 4, 5]
+    thetas = [300, 500, 257, 300, 1000, 64, 300, 300, 999, 300, 300, 128, 300, 300, 700, 300]
+    probs = [(g.handle, t.seeds, b, th, t.seed) for g, t, b, th in zip(graphs, insts, bs, thetas)]
+    case("batched AG over 16 instances")
+    res = gpu.imin_greedy_batch(probs)
+    for i, (t, g, b, th) in enumerate(zip(insts, graphs, bs, thetas)):
+        B, st = res[i]
+        case(f"instance {i} ({t.name}, n={t.n}, b={b}, theta={th}) against the oracle")
+        Bo, calls, so = orc.greedy(t.n, t.row_ptr, t.col, t.prob, t.seeds, b, th, t.seed, 0)
+        assert list(B) == list(Bo), i
+        assert st["samples"] == so["samples"] and st["reached"] == so["reached"], i
+        assert st["edges_scanned"] == so["edges_scanned"], i
+        assert st["live_edges"] == so["live_edges"], i
+        Bp, sp = g.greedy(t.seeds, b, th, t.seed, gpu.IMIN_AG)
+        assert list(Bp) == list(B), i
+    for g in graphs:
+        g.close()
+
+
+def test_batch_with_handed_over_samples_and_existing_scratch(gpu, batch16):
+    """Instances whose samples outgrow the wave kernel, one of whose graphs already holds
+    workgroup scratch (and stale seed stamps) from an earlier plain call."""
+    t0, t1 = batch16[0], batch16[1]
+    prp, pc, pp = _path_graph()
+    drp, dc, dp = _dense_graph()
+    gpath = gpu.Graph(prp, pc, pp)
+    gdense = gpu.Graph(drp, dc, dp)
+    g0 = gpu.Graph(t0.row_ptr, t0.col, t0.prob)
+    g1 = gpu.Graph(t1.row_ptr, t1.col, t1.prob)
+    case("plain call on the dense graph with other seeds, leaving scratch and stamps")
+    gdense.greedy([5, 6], 2, 30, 9, gpu.IMIN_AG)
+    probs = [(gpath.handle, [0], 4, 60, 1), (gdense.handle, [0], 3, 70, 2),
+             (g0.handle, t0.seeds, 3, 200, 3), (g1.handle, t1.seeds, 2, 300, 4)]
+    case("batch of 4 with handed-over samples")
+    res = gpu.imin_greedy_batch(probs)
+    cases = [(300, prp, pc, pp), (40, drp, dc, dp), (t0.n, t0.row_ptr, t0.col, t0.prob),
+             (t1.n, t1.row_ptr, t1.col, t1.prob)]
+    for i, ((n, rp, c, p), (_, S, b, th, key)) in enumerate(zip(cases, probs)):
+        Bo, calls, so = orc.greedy(n, rp, c, p, np.asarray(S, np.int32), b, th, key, 0)
+        B, st = res[i]
+        assert list(B) == list(Bo), i
+        assert st["reached"] == so["reached"], i
+    # round 0 of the path reaches 299 vertices in every sample (all handed over); once its
+    # first vertex is blocked nothing is reached and the wave kernel finishes the rest
+    assert res[0][1]["wave_samples"] == 3 * 60
+    # the handles keep working for plain calls afterwards
+    case("plain decrease after the batch")
+    D, _ = gdense.decrease([0], None, 50, 0)
+    Do, _ = orc.decrease(40, drp, dc, dp, [0], None, 50, 0)
+    assert np.array_equal(D, Do)
+    for g in (gpath, gdense, g0, g1):
+        g.close()
+
+
+def test_batch_errors_leave_outputs_untouched(gpu):
+    rp, c, p = _path_graph(20)
+    g = gpu.Graph(rp, c, p)
+    h = gpu.Graph(rp, c, p)
+    with pytest.raises(gpu.IminError) as e:
+        gpu.imin_greedy_batch([(g.handle, [0], 2, 10, 0), (g.handle, [1], 2, 10, 0)])
+    assert e.value.status == gpu.IMIN_EINVAL
+    with pytest.raises(gpu.IminError) as e:
+        gpu.imin_greedy_batch([(g.handle, [0], 2, 10, 0)], mode=gpu.IMIN_GR)
+    assert e.value.status == gpu.IMIN_EINVAL
+    for bad in ((g.handle, [25], 2, 10, 0), (g.handle, [0], -1, 10, 0), (g.handle, [0], 2, 0, 0)):
+        with pytest.raises(gpu.IminError) as e:
+            gpu.imin_greedy_batch([(h.handle, [0], 1, 10, 0), bad])
+        assert e.value.status == gpu.IMIN_EINVAL
+    with pytest.raises(gpu.IminError) as e:
+        gpu.imin_greedy_batch([(g.handle, [0], 1, 2**31, 0), (h.handle, [0], 1, 2**31, 0)])
+    assert e.value.status == gpu.IMIN_ERANGE
+    case("batch after rejected calls")
+    res = gpu.imin_greedy_batch([(g.handle, [0], 2, 10, 0), (h.handle, [3], 2, 10, 1)])
+    assert list(res[0][0]) == [1, 2] and list(res[1][0]) == [4, 0]
+    g.close()
+    h.close()

@@ -1,9 +1,9 @@
 """GPU path (libimin through its C ABI) against the CPU oracle, bit-exact.
 
 Decrease counts D are integer sums, so they must equal the oracle's exactly, as must
-the work counters and every greedy choice. Cases span several workgroup chunks of the
-frontier (256 vertices), ragged quads at row ends, the spill path, launch shapes, and
-degenerate inputs. At the full 4M-vertex size the oracle checks a few samples exactly and
+the work counters and every greedy choice. Cases span several frontier chunks, ragged quads
+at row ends, the wave-per-sample kernel and its hand-over to the workgroup kernel, the
+large-scratch spill path, launch shapes, and degenerate inputs. At the full 4M-vertex size the oracle checks a few samples exactly and
 properties that hold at any size check the full-theta launch the benchmark times.
 """
 import numpy as np
@@ -65,7 +65,9 @@ def test_toy_decrease_and_greedy(gpu):
 def test_launch_shapes_and_spill_give_identical_counts(gpu, tiny):
     t = tiny
     g = gpu.Graph(t.row_ptr, t.col, t.prob)
+    g.set_small(0)  # workgroup kernel only
     D0, s0 = check_decrease(g, t.n, t.row_ptr, t.col, t.prob, t.seeds, None, 700, 9, "auto")
+    assert s0["wave_samples"] == 0
     for slots, cap in ((1, 0), (3, 0), (37, 0), (512, 0), (5, 1), (64, 2), (1, 1)):
         case(f"shape slots={slots} extra_cap={cap}")
         g.set_launch(slots, cap)
@@ -74,6 +76,16 @@ def test_launch_shapes_and_spill_give_identical_counts(gpu, tiny):
         assert s["reached"] == s0["reached"] and s["live_edges"] == s0["live_edges"]
         if cap == 1:
             assert s["spilled"] > 0
+    g.set_launch(0, 0)
+    for waves, ql in ((1, 0), (4, 1), (8, 3), (20, 0), (32, 100000)):
+        case(f"wave kernel waves_per_cu={waves} quad_limit={ql}")
+        g.set_small(1, waves, ql)
+        D, s = g.decrease(t.seeds, None, 700, 9)
+        assert np.array_equal(D, D0)
+        assert s["reached"] == s0["reached"] and s["live_edges"] == s0["live_edges"]
+        assert s["edges_scanned"] == s0["edges_scanned"]
+        if ql == 0 or ql > 1000:  # tiny quad limits hand every seed frontier over
+            assert s["wave_samples"] > 0
     g.close()
 
 
@@ -126,6 +138,12 @@ def test_edge_cases(gpu, item):
     g = gpu.Graph(row_ptr, col, prob)
     for theta, key in ((1, 0), (97, 3), (1000, 2**33 + 1)):
         check_decrease(g, n, row_ptr, col, prob, seeds, blocked, theta, key, label)
+    # wave kernel off, and on with every frontier chunk handed over at once
+    for enable, ql in ((0, 0), (1, 1), (1, 0)):
+        g.set_small(enable, 0, ql)
+        check_decrease(g, n, row_ptr, col, prob, seeds, blocked, 97, 3,
+                       f"{label}/small={enable},{ql}")
+    g.set_small(0)
     g.set_launch(2, 1)
     check_decrease(g, n, row_ptr, col, prob, seeds, blocked, 97, 3, label + "/spill")
     g.close()
