@@ -184,12 +184,18 @@ typedef struct {
  * wave-per-sample launch over all their samples (samples that outgrow it go to the
  * workgroup kernel of their own graph), then one argmax per instance. Instance i's result
  * is bit-identical to imin_greedy(inst[i].g, S, nS, b, theta, seed, IMIN_AG, ...).
- *   mode   IMIN_AG only (IMIN_EINVAL otherwise).
- *   count  >= 1; the total of theta over the batch must stay below 2^31 (IMIN_ERANGE).
+ *   mode          IMIN_AG only (IMIN_EINVAL otherwise).
+ *   count         >= 1; the total of theta over the batch must not exceed 2^31 (IMIN_ERANGE).
+ *   waves_per_cu  resident waves per compute unit of the wave kernel (0: default 20).
+ *   quad_limit    frontier-chunk quad limit of the wave kernel, as for imin_set_small
+ *                 (0: default 2048).
+ * The launch values change speed only, never results; the graphs' own imin_set_small
+ * settings do not apply here.
  * Errors: IMIN_EINVAL (any instance invalid as for imin_greedy, a graph repeated, NULL
- * inst), IMIN_ERANGE, IMIN_ENOMEM, IMIN_EDEVICE.
+ * inst, negative launch values), IMIN_ERANGE, IMIN_ENOMEM, IMIN_EDEVICE.
  */
-IMIN_API int imin_greedy_batch(imin_instance *inst, int32_t count, int mode);
+IMIN_API int imin_greedy_batch(imin_instance *inst, int32_t count, int mode,
+                               int32_t waves_per_cu, int32_t quad_limit);
 
 /* Human-readable text of a status code (static storage). */
 IMIN_API const char *imin_strerror(int status);

@@ -74,7 +74,7 @@ def load() -> ctypes.CDLL:
     lib.imin_set_small.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.imin_set_small.restype = ctypes.c_int
     lib.imin_greedy_batch.argtypes = [ctypes.POINTER(imin_instance), ctypes.c_int32,
-                                      ctypes.c_int]
+                                      ctypes.c_int, ctypes.c_int32, ctypes.c_int32]
     lib.imin_greedy_batch.restype = ctypes.c_int
     lib.imin_strerror.argtypes = [ctypes.c_int]
     lib.imin_strerror.restype = ctypes.c_char_p
@@ -150,7 +150,8 @@ def imin_greedy(handle: int, seeds, b: int, theta: int, seed: int, mode: int):
     return out[: nb[0]].copy(), st.as_dict()
 
 
-def imin_greedy_batch(problems, mode: int = IMIN_AG):
+def imin_greedy_batch(problems, mode: int = IMIN_AG, waves_per_cu: int = 0,
+                      quad_limit: int = 0):
     """AdvancedGreedy on many problems at once. ``problems``: sequence of
     (handle, seeds, b, theta, seed). Returns a list of (blockers, stats dict)."""
     k = len(problems)
@@ -173,7 +174,7 @@ def imin_greedy_batch(problems, mode: int = IMIN_AG):
         arr[i].blockers = _p(out)
         arr[i].n_blockers = _p(nb)
         arr[i].stats = ctypes.pointer(st)
-    rc = load().imin_greedy_batch(arr, k, int(mode))
+    rc = load().imin_greedy_batch(arr, k, int(mode), int(waves_per_cu), int(quad_limit))
     if rc != IMIN_OK:
         raise IminError("imin_greedy_batch", rc)
     return [(out[: nb[0]].copy(), st.as_dict()) for out, nb, st in outs]

@@ -22,8 +22,12 @@ struct imin_graph {
     std::vector<int32_t> row_ptr;  // host copies: out-neighbours of the seeds (GR)
     std::vector<int32_t> col;
     int32_t *d_row_ptr = nullptr;
-    uint4 *d_col4 = nullptr;   // edge targets, 4 per quad, padded to a whole quad
-    uint4 *d_thr4 = nullptr;   // live thresholds, same layout
+    uint4 *d_col4 = nullptr;      // edge targets, 4 per quad, padded to a whole quad
+    uint4 *d_thr4 = nullptr;      // working live thresholds, same layout: 0 on every edge into
+                                  // a vertex of `masked`
+    uint4 *d_thr_orig = nullptr;  // the thresholds ceil(p * 2^24) as created
+    int32_t *d_in_ptr = nullptr;  // in-edges of v: d_in_edge[d_in_ptr[v] .. d_in_ptr[v+1])
+    int32_t *d_in_edge = nullptr; // edge ids, grouped by target
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int32_t words = 0;                       // 32-bit words of a vertex bitmap
@@ -52,9 +56,10 @@ struct imin_graph {
     int32_t B_cap = 0;
     int32_t *d_x = nullptr;
     Workspace main_ws, big_ws;
-    std::vector<int32_t> marked;   // vertices stamped kInelig in every slot map
-    bool marks_valid = true;       // false after a call that stopped half-way
-    int32_t *d_list = nullptr;     // n: vertex lists for stamping
+    std::vector<int32_t> masked;       // vertices whose in-edges have threshold 0 in d_thr4
+    std::vector<int32_t> mask_prev;    // the previous call's list, kept while copies run
+    bool mask_known = true;            // false while a call runs, and after one that failed
+    int32_t *d_list = nullptr;         // 2n: device copies of the two lists above
     std::vector<hipEvent_t> kev;  // pairs around each decrease launch of the current call
     size_t kev_used = 0;
     int32_t force_slots = 0;
@@ -70,6 +75,8 @@ constexpr int32_t kDefaultQuadLimit = 2048;
 // In automatic mode the wave kernel is dropped for a graph once fewer than this share of
 // a round's samples finished in it.
 constexpr double kSmallKeepShare = 0.5;
+// Workgroup-kernel slots while the wave kernel takes the samples first (it leaves few).
+constexpr int32_t kSmallModeSlots = 64;
 // The per-launch work counter is 32-bit and every workgroup takes one index past the end.
 constexpr uint32_t kMaxTheta = 1u << 31;
 
@@ -137,16 +144,7 @@ int alloc_ws(imin_graph *g, Workspace &ws, int32_t slots, int64_t lcap, int64_t 
 // Per-slot scratch: every local array holds all n vertices plus the root, so only the
 // extra-edge list can overflow. Its default capacity covers a quarter of the vertices; a
 // graph whose m is below that can never overflow and needs no spill path.
-// After a call that stopped half-way the slot-map stamps are unknown: drop the scratch.
-void reset_stale(imin_graph *g)
-{
-    if (!g->marks_valid) {
-        free_ws(g->main_ws);
-        free_ws(g->big_ws);
-        g->marked.clear();
-        g->marks_valid = true;
-    }
-}
+bool small_enabled(const imin_graph *g);
 
 // max_slots > 0 caps a new allocation (an existing one of the right shape is kept).
 int size_workspaces(imin_graph *g, int32_t max_slots)
@@ -165,9 +163,12 @@ int size_workspaces(imin_graph *g, int32_t max_slots)
         const size_t by_mem = std::max<size_t>(1, (free_b / 2) / per);
         slots = (int32_t)std::min<size_t>((size_t)2 * g->num_cus, by_mem);
         if (max_slots > 0) slots = std::min(slots, max_slots);
-        if (g->main_ws.slots > 0 && g->main_ws.lcap == lcap && g->main_ws.xcap == xcap &&
-            (g->main_ws.slots <= slots || max_slots > 0))
-            slots = g->main_ws.slots;  // keep a working allocation
+        // keep a working allocation that is at least as large, or a full-size one that the
+        // free memory now sizes slightly differently
+        const int32_t have = g->main_ws.slots;
+        if (have > 0 && g->main_ws.lcap == lcap && g->main_ws.xcap == xcap &&
+            (have >= slots || (max_slots == 0 && have > kSmallModeSlots)))
+            slots = have;
     }
     int rc = alloc_ws(g, g->main_ws, slots, lcap, xcap);
     if (rc) return rc;
@@ -182,8 +183,7 @@ int size_workspaces(imin_graph *g, int32_t max_slots)
 
 int prepare_workspaces(imin_graph *g)
 {
-    reset_stale(g);
-    return size_workspaces(g, 0);
+    return size_workspaces(g, small_enabled(g) ? kSmallModeSlots : 0);
 }
 
 // Keep every slot's 32-bit epoch from wrapping: a launch of theta samples raises any slot's
@@ -197,8 +197,7 @@ int guard_epochs(imin_graph *g, Workspace &ws, uint32_t theta)
     }
     if (!ok(hipMemsetAsync(ws.map, 0, (size_t)ws.slots * g->n * sizeof(imin::SlotEntry),
                            g->stream)) ||
-        !ok(hipMemsetAsync(ws.epoch, 0, (size_t)ws.slots * sizeof(uint32_t), g->stream)) ||
-        !ok(imin::launch_mark_bitmap(ws.map, ws.slots, g->n, g->d_inelig, g->stream)))
+        !ok(hipMemsetAsync(ws.epoch, 0, (size_t)ws.slots * sizeof(uint32_t), g->stream)))
         return IMIN_EDEVICE;
     ws.epochs_used = theta;
     return IMIN_OK;
@@ -235,18 +234,18 @@ bool small_enabled(const imin_graph *g)
     return !g->small_auto_off;
 }
 
-int small_grid(const imin_graph *g)
+int small_grid(int num_cus, int32_t waves_per_cu)
 {
-    const int32_t wpc = g->small_waves_per_cu > 0 ? g->small_waves_per_cu
-                                                  : kDefaultSmallWavesPerCu;
+    const int32_t wpc = waves_per_cu > 0 ? waves_per_cu : kDefaultSmallWavesPerCu;
     const int per_cu = std::max(1, (wpc + imin::kSmallWaves - 1) / imin::kSmallWaves);
-    return g->num_cus * per_cu;
+    return num_cus * per_cu;
 }
 
-int32_t quad_limit(const imin_graph *g)
-{
-    return g->quad_limit > 0 ? g->quad_limit : kDefaultQuadLimit;
-}
+int small_grid(const imin_graph *g) { return small_grid(g->num_cus, g->small_waves_per_cu); }
+
+int32_t quad_limit(int32_t q) { return q > 0 ? q : kDefaultQuadLimit; }
+
+int32_t quad_limit(const imin_graph *g) { return quad_limit(g->quad_limit); }
 
 int ensure_B(imin_graph *g, int32_t b)
 {
@@ -294,6 +293,8 @@ int upload_call_state(imin_graph *g, const std::vector<int32_t> &seeds,
     I.row_ptr = g->d_row_ptr;
     I.col4 = g->d_col4;
     I.thr4 = g->d_thr4;
+    I.in_ptr = g->d_in_ptr;
+    I.in_edge = g->d_in_edge;
     I.inelig = g->d_inelig;
     I.seeds = g->d_seeds;
     I.D = g->d_D;
@@ -309,37 +310,46 @@ int upload_call_state(imin_graph *g, const std::vector<int32_t> &seeds,
     if (!ok(hipMemcpyAsync(g->d_inst, &g->h_inst, sizeof(imin::InstanceDesc),
                            hipMemcpyHostToDevice, g->stream)))
         return IMIN_EDEVICE;
-    // Slot-map stamps: clear the previous call's seeds and blockers, stamp the new ones.
-    Workspace *wss[2] = {&g->main_ws, &g->big_ws};
-    g->marks_valid = false;
-    for (Workspace *ws : wss) {
-        if (ws->slots == 0) continue;
-        if (!g->marked.empty()) {
-            if (!ok(hipMemcpyAsync(g->d_list, g->marked.data(), g->marked.size() * sizeof(int32_t),
-                                   hipMemcpyHostToDevice, g->stream)) ||
-                !ok(imin::launch_set_stamps(ws->map, ws->slots, g->n, g->d_list,
-                                            (int32_t)g->marked.size(), 0u, g->stream)))
-                return IMIN_EDEVICE;
-        }
-        if (!ok(imin::launch_mark_bitmap(ws->map, ws->slots, g->n, g->d_inelig, g->stream)))
+    // Working thresholds: restore the in-edges the previous call masked (all of them when
+    // that call stopped half-way), then mask the in-edges of this call's seeds and blocked
+    // vertices.
+    uint32_t *thr = reinterpret_cast<uint32_t *>(g->d_thr4);
+    const uint32_t *orig = reinterpret_cast<const uint32_t *>(g->d_thr_orig);
+    g->mask_prev.swap(g->masked);
+    if (!g->mask_known) {
+        const int64_t quads = std::max<int64_t>(((int64_t)g->m + 3) / 4, 1);
+        if (!ok(hipMemcpyAsync(g->d_thr4, g->d_thr_orig, (size_t)quads * sizeof(uint4),
+                               hipMemcpyDeviceToDevice, g->stream)))
+            return IMIN_EDEVICE;
+    } else if (!g->mask_prev.empty()) {
+        if (!ok(hipMemcpyAsync(g->d_list, g->mask_prev.data(),
+                               g->mask_prev.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                               g->stream)) ||
+            !ok(imin::launch_mask_list(thr, orig, g->d_in_ptr, g->d_in_edge, g->d_list,
+                                       (int32_t)g->mask_prev.size(), 1, g->stream)))
             return IMIN_EDEVICE;
     }
-    g->marked.clear();
+    g->mask_known = false;
+    g->masked.clear();
     for (int32_t v = 0; v < g->n; ++v)
-        if ((inelig[v >> 5] >> (v & 31)) & 1u) g->marked.push_back(v);
+        if ((inelig[v >> 5] >> (v & 31)) & 1u) g->masked.push_back(v);
+    if (!g->masked.empty() &&
+        (!ok(hipMemcpyAsync(g->d_list + g->n, g->masked.data(), g->masked.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, g->stream)) ||
+         !ok(imin::launch_mask_list(thr, orig, g->d_in_ptr, g->d_in_edge, g->d_list + g->n,
+                                    (int32_t)g->masked.size(), 0, g->stream))))
+        return IMIN_EDEVICE;
     return IMIN_OK;
 }
 
-// A vertex joins (value kInelig) or leaves (value 0) the seed/blocked stamps of all slots;
-// v_dev, when non-null, holds the vertex id on the device.
-int stamp_vertex(imin_graph *g, int32_t v, const int32_t *v_dev, uint32_t value)
+// The call ended with the seeds and `blockers` masked.
+void end_masks(imin_graph *g, const std::vector<int32_t> &blockers)
 {
-    Workspace *wss[2] = {&g->main_ws, &g->big_ws};
-    for (Workspace *ws : wss)
-        if (!ok(imin::launch_set_stamp(ws->map, ws->slots, g->n, v, v_dev, value, g->stream)))
-            return IMIN_EDEVICE;
-    return IMIN_OK;
+    for (int32_t v : blockers) g->masked.push_back(v);
+    g->mask_known = true;
 }
+
+uint32_t *thr_w(imin_graph *g) { return reinterpret_cast<uint32_t *>(g->d_thr4); }
 
 // A fresh pair of timing events for one round's decrease launches.
 int kernel_events(imin_graph *g, hipEvent_t *a, hipEvent_t *b)
@@ -479,8 +489,10 @@ int auto_check(imin_graph *g)
     if (!ok(hipMemcpyAsync(st, g->d_stats, sizeof(st), hipMemcpyDeviceToHost, g->stream)) ||
         !ok(hipStreamSynchronize(g->stream)))
         return IMIN_EDEVICE;
-    if ((double)st[5] < kSmallKeepShare * (double)st[0]) g->small_auto_off = true;
-    return IMIN_OK;
+    if ((double)st[5] >= kSmallKeepShare * (double)st[0]) return IMIN_OK;
+    g->small_auto_off = true;
+    // the workgroup kernel now takes every sample: give it the full slot count
+    return size_workspaces(g, 0);
 }
 
 int begin_call(imin_graph *g)
@@ -501,6 +513,9 @@ void destroy(imin_graph *g)
     dfree(g->d_row_ptr);
     dfree(g->d_col4);
     dfree(g->d_thr4);
+    dfree(g->d_thr_orig);
+    dfree(g->d_in_ptr);
+    dfree(g->d_in_edge);
     dfree(g->d_inelig);
     dfree(g->d_cand);
     dfree(g->d_seeds);
@@ -557,19 +572,11 @@ struct BatchItem {
     int32_t rounds = 0;
 };
 
-// Scratch for a graph's first spilled samples of a batched call. The new slot maps start
-// from the seed/blocked bitmap as it stands on the device, blockers of earlier rounds
-// included.
+// Scratch for a graph's first spilled samples of a batched call.
 int batch_workspace(imin_graph *g)
 {
     if (g->main_ws.slots > 0) return IMIN_OK;
-    int rc = size_workspaces(g, kBatchSlots);
-    if (rc) return rc;
-    Workspace *wss[2] = {&g->main_ws, &g->big_ws};
-    for (Workspace *ws : wss)
-        if (!ok(imin::launch_mark_bitmap(ws->map, ws->slots, g->n, g->d_inelig, g->stream)))
-            return IMIN_EDEVICE;
-    return IMIN_OK;
+    return size_workspaces(g, kBatchSlots);
 }
 
 }  // namespace
@@ -638,6 +645,21 @@ int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
         hcol[(size_t)e] = (uint32_t)col[e];
         hthr[(size_t)e] = live_threshold(prob[e]);
     }
+    // in-edge index: edge ids grouped by target (counting sort)
+    std::vector<int32_t> in_ptr, in_edge;
+    try {
+        in_ptr.assign((size_t)n + 1, 0);
+        in_edge.assign((size_t)std::max(m, 1), 0);
+    } catch (...) {
+        delete g;
+        return IMIN_ENOMEM;
+    }
+    for (int32_t e = 0; e < m; ++e) ++in_ptr[(size_t)col[e] + 1];
+    for (int32_t v = 0; v < n; ++v) in_ptr[(size_t)v + 1] += in_ptr[(size_t)v];
+    {
+        std::vector<int32_t> fill(in_ptr.begin(), in_ptr.end() - 1);
+        for (int32_t e = 0; e < m; ++e) in_edge[(size_t)fill[(size_t)col[e]]++] = e;
+    }
     g->words = (n + 31) / 32;
     bool good =
         ok(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking)) &&
@@ -645,10 +667,13 @@ int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
         ok(hipMalloc(&g->d_row_ptr, (size_t)(n + 1) * sizeof(int32_t))) &&
         ok(hipMalloc(&g->d_col4, hcol.size() * sizeof(uint32_t))) &&
         ok(hipMalloc(&g->d_thr4, hthr.size() * sizeof(uint32_t))) &&
+        ok(hipMalloc(&g->d_thr_orig, hthr.size() * sizeof(uint32_t))) &&
+        ok(hipMalloc(&g->d_in_ptr, in_ptr.size() * sizeof(int32_t))) &&
+        ok(hipMalloc(&g->d_in_edge, in_edge.size() * sizeof(int32_t))) &&
         ok(hipMalloc(&g->d_inelig, (size_t)g->words * sizeof(uint32_t))) &&
         ok(hipMalloc(&g->d_cand, (size_t)g->words * sizeof(uint32_t))) &&
         ok(hipMalloc(&g->d_seeds, (size_t)n * sizeof(int32_t))) &&
-        ok(hipMalloc(&g->d_list, (size_t)n * sizeof(int32_t))) &&
+        ok(hipMalloc(&g->d_list, 2 * (size_t)n * sizeof(int32_t))) &&
         ok(hipMalloc(&g->d_D, (size_t)n * sizeof(unsigned long long))) &&
         ok(hipMalloc(&g->d_stats, kStats * sizeof(unsigned long long))) &&
         ok(hipMalloc(&g->d_ctrl, 4 * sizeof(uint32_t))) &&
@@ -667,6 +692,12 @@ int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
         !ok(hipMemcpy(g->d_col4, hcol.data(), hcol.size() * sizeof(uint32_t),
                       hipMemcpyHostToDevice)) ||
         !ok(hipMemcpy(g->d_thr4, hthr.data(), hthr.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice)) ||
+        !ok(hipMemcpy(g->d_thr_orig, hthr.data(), hthr.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice)) ||
+        !ok(hipMemcpy(g->d_in_ptr, in_ptr.data(), in_ptr.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice)) ||
+        !ok(hipMemcpy(g->d_in_edge, in_edge.data(), in_edge.size() * sizeof(int32_t),
                       hipMemcpyHostToDevice))) {
         destroy(g);
         return IMIN_EDEVICE;
@@ -722,7 +753,7 @@ int imin_decrease(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *bl
     imin_stats st;
     rc = finish_call(g, &st);
     if (rc) return rc;
-    g->marks_valid = true;
+    end_masks(g, {});
     if (small && g->small_mode == -1 &&
         (double)st.wave_samples < kSmallKeepShare * (double)st.samples)
         g->small_auto_off = true;
@@ -770,10 +801,9 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
             ++call;
             if (!ok(imin::launch_argmax_apply(g->d_D, g->d_inelig, 0, g->n, g->d_part_d,
                                               g->d_part_i, g->parts, g->d_inelig, nullptr,
-                                              g->d_B, r, g->d_x, g->stream)))
+                                              g->d_B, r, g->d_x, thr_w(g), g->d_in_ptr,
+                                              g->d_in_edge, g->stream)))
                 return IMIN_EDEVICE;
-            rc = stamp_vertex(g, 0, g->d_x, imin::kInelig);
-            if (rc) return rc;
         }
         B.assign((size_t)rounds, -1);
         if (rounds > 0 &&
@@ -808,10 +838,9 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
             ++call;
             if (!ok(imin::launch_argmax_apply(g->d_D, g->d_cand, 1, g->n, g->d_part_d,
                                               g->d_part_i, g->parts, g->d_inelig, g->d_cand,
-                                              g->d_B, r, g->d_x, g->stream)))
+                                              g->d_B, r, g->d_x, thr_w(g), g->d_in_ptr,
+                                              g->d_in_edge, g->stream)))
                 return IMIN_EDEVICE;
-            rc = stamp_vertex(g, 0, g->d_x, imin::kInelig);
-            if (rc) return rc;
         }
         B.assign((size_t)k, -1);
         if (k > 0) {
@@ -827,9 +856,12 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
             const int32_t u = snapshot[(size_t)i];
             const int32_t slot =
                 (int32_t)(std::find(B.begin(), B.end(), u) - B.begin());
-            if (!ok(imin::launch_set_bit(g->d_inelig, u, 0, g->stream))) return IMIN_EDEVICE;
-            rc = stamp_vertex(g, u, nullptr, 0u);
-            if (rc) return rc;
+            if (!ok(imin::launch_set_bit(g->d_inelig, u, 0, g->stream)) ||
+                !ok(imin::launch_mask_vertex(thr_w(g), reinterpret_cast<const uint32_t *>(
+                                                           g->d_thr_orig),
+                                             g->d_in_ptr, g->d_in_edge, u, nullptr, 1,
+                                             g->stream)))
+                return IMIN_EDEVICE;
             rc = decrease_round(g, ns, theta, seed, call);
             if (rc) return rc;
             if (call == 0) {
@@ -839,10 +871,9 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
             ++call;
             if (!ok(imin::launch_argmax_apply(g->d_D, g->d_inelig, 0, g->n, g->d_part_d,
                                               g->d_part_i, g->parts, g->d_inelig, nullptr,
-                                              g->d_B, slot, g->d_x, g->stream)))
+                                              g->d_B, slot, g->d_x, thr_w(g), g->d_in_ptr,
+                                              g->d_in_edge, g->stream)))
                 return IMIN_EDEVICE;
-            rc = stamp_vertex(g, 0, g->d_x, imin::kInelig);
-            if (rc) return rc;
             int32_t x = -1;
             if (!ok(hipMemcpyAsync(&x, g->d_x, sizeof(int32_t), hipMemcpyDeviceToHost,
                                    g->stream)) ||
@@ -858,9 +889,7 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
     if (rc) return rc;
     for (int32_t v : B)
         if (v < 0) return IMIN_EDEVICE;
-    // the stamped set is now the seeds plus the final blockers
-    for (int32_t v : B) g->marked.push_back(v);
-    g->marks_valid = true;
+    end_masks(g, B);
     std::copy(B.begin(), B.end(), blockers);
     *n_blockers = (int32_t)B.size();
     if (stats) *stats = st;
@@ -877,9 +906,11 @@ int imin_set_small(imin_graph *g, int32_t enable, int32_t waves_per_cu, int32_t 
     return IMIN_OK;
 }
 
-int imin_greedy_batch(imin_instance *inst, int32_t count, int mode)
+int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, int32_t waves_per_cu,
+                      int32_t quad_limit_)
 {
-    if (!inst || count <= 0 || mode != IMIN_AG) return IMIN_EINVAL;
+    if (!inst || count <= 0 || mode != IMIN_AG || waves_per_cu < 0 || quad_limit_ < 0)
+        return IMIN_EINVAL;
     std::vector<BatchItem> items((size_t)count);
     std::vector<imin_graph *> graphs;
     uint64_t theta_sum = 0;
@@ -919,7 +950,6 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode)
     for (int32_t i = 0; i < count; ++i) {
         BatchItem &it = items[(size_t)i];
         imin_graph *g = it.g;
-        reset_stale(g);
         int rc = ensure_ovf(g, it.in->theta);
         if (rc) return rc;
         rc = ensure_sj(g, it.in->theta);
@@ -962,13 +992,15 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode)
         s.ninst = active;
         s.total = prefix[(size_t)active];
         s.round = (uint32_t)r;
-        s.quad_limit = quad_limit(g0);
+        s.quad_limit = quad_limit(quad_limit_);
         s.next = d_ctrl.p + 0;
         s.spill_inst = d_si.p;
         s.spill_j = d_sj.p;
         s.spill_count = d_ctrl.p + 1;
         s.error = d_ctrl.p + 2;
-        if (!ok(imin::launch_decrease_small(s, small_grid(g0), bs))) return IMIN_EDEVICE;
+        if (!ok(imin::launch_decrease_small(s, small_grid(g0->num_cus, waves_per_cu), bs)) ||
+            !ok(hipEventRecord(k1, bs)))
+            return IMIN_EDEVICE;
         uint32_t nspill = 0;
         if (!ok(hipMemcpyAsync(&nspill, d_ctrl.p + 1, sizeof(uint32_t), hipMemcpyDeviceToHost,
                                bs)) ||
@@ -988,6 +1020,10 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode)
                 if (spill_i[k] >= (uint32_t)active) return IMIN_EDEVICE;
                 lists[spill_i[k]].push_back(spill_j[k]);
             }
+            hipEvent_t w0, w1;
+            rc = kernel_events(g0, &w0, &w1);
+            if (rc) return rc;
+            if (!ok(hipEventRecord(w0, bs))) return IMIN_EDEVICE;
             for (int32_t i = 0; i < active; ++i) {
                 std::vector<uint32_t> &l = lists[(size_t)i];
                 if (l.empty()) continue;
@@ -1007,16 +1043,9 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode)
                                   it.in->seed + (uint64_t)r, g->d_sj, g->d_sctrl + 1);
                 if (rc) return rc;
             }
+            if (!ok(hipEventRecord(w1, bs))) return IMIN_EDEVICE;
         }
-        if (!ok(hipEventRecord(k1, bs)) || !ok(imin::launch_batch_argmax(d_table.p, active, r, bs)))
-            return IMIN_EDEVICE;
-        for (int32_t i = 0; i < active; ++i) {
-            imin_graph *g = items[(size_t)i].g;
-            if (g->main_ws.slots > 0) {
-                rc = stamp_vertex(g, 0, g->d_x, imin::kInelig);
-                if (rc) return rc;
-            }
-        }
+        if (!ok(imin::launch_batch_argmax(d_table.p, active, r, bs))) return IMIN_EDEVICE;
     }
     // Results: every graph's blocker slots, counters and error flag, then one wait.
     std::vector<std::vector<int32_t>> B((size_t)count);
@@ -1054,8 +1083,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode)
     }
     for (int32_t i = 0; i < count; ++i) {
         BatchItem &it = items[(size_t)i];
-        for (int32_t v : B[(size_t)i]) it.g->marked.push_back(v);
-        it.g->marks_valid = true;
+        end_masks(it.g, B[(size_t)i]);
         std::copy(B[(size_t)i].begin(), B[(size_t)i].end(), it.in->blockers);
         *it.in->n_blockers = it.rounds;
         if (it.in->stats) {

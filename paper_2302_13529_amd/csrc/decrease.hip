@@ -7,7 +7,8 @@
 //      (Definition 4, live-edge sampling). One Philox call serves the 4 edges of a 32-byte
 //      edge quad, and a lane works on one quad at a time;
 //   2. runs a level-synchronous BFS from the merged seed (Section V, multiple seeds to one
-//      seed) over live edges whose target is neither a seed nor blocked (Definition 2).
+//      seed) over live edges. An edge into a seed or a blocked vertex (Definition 2) has
+//      threshold 0 in the call's threshold array, so it is never live.
 //      Reached vertices get local ids in BFS order; the BFS parent of each is kept, and
 //      every other live edge between reached vertices is kept in an "extra" list;
 //   3. computes the dominator tree of the reached subgraph (Section V-B3): starting from
@@ -80,16 +81,14 @@ struct Shared {
     unsigned live;
 };
 
-// Live edge src -> w. Returns false when w is a seed or blocked (stamp kInelig); otherwise
-// w is claimed for this sample if it was not yet reached, or the edge is kept as an extra
-// edge (edges from the merged seed never matter for dominators: their targets are its
-// children).
-__device__ __forceinline__ bool visit(const DecreaseArgs &a, const SlotView &sv, Shared &sh,
+// Live edge src -> w: w is claimed for this sample if it was not yet reached, or the edge is
+// kept as an extra edge (edges from the merged seed never matter for dominators: their
+// targets are its children).
+__device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv, Shared &sh,
                                       int w, int src, uint32_t epoch)
 {
     const uint32_t old = __hip_atomic_fetch_max(&sv.map[w].stamp, epoch, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (old == kInelig) return false;
     if (old != epoch) {
         const int id = atomicAdd(&sh.tail, 1);
         if (id < a.ws.lcap) {
@@ -108,7 +107,6 @@ __device__ __forceinline__ bool visit(const DecreaseArgs &a, const SlotView &sv,
         if (x < a.ws.xcap) sv.extra[x] = make_int2(src, w);
         else sh.ovf = 1;
     }
-    return true;
 }
 
 // Quad q of the current chunk: the frontier entry it belongs to and its edge quad index.
@@ -128,11 +126,12 @@ __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView
                                            uint32_t mask, uint4 col, int src, uint32_t epoch,
                                            uint32_t &live)
 {
+    live += (uint32_t)__builtin_popcount(mask);
     while (mask) {
         const int i = __builtin_ctz(mask);
         mask &= mask - 1;
         const uint32_t c = i == 0 ? col.x : i == 1 ? col.y : i == 2 ? col.z : col.w;
-        if (visit(a, sv, sh, (int)c, src, epoch)) ++live;
+        visit(a, sv, sh, (int)c, src, epoch);
     }
 }
 

@@ -8,11 +8,14 @@ namespace imin {
 
 constexpr int kBlock = 1024;  // threads per workgroup; one workgroup works on one sample at a time
 
+// Seeds and blocked vertices: every edge into such a vertex has live threshold 0 in the
+// graph's working threshold array while a call runs, so it is never live, which is exactly
+// the rule that a live edge never activates a seed again or a blocked vertex (Definition 2;
+// each edge's coin is independent of the others). The kernels therefore never test it.
+
 // Per slot and vertex: the epoch of the sample that last reached the vertex, and its
-// local id in that sample. Both halves live in one 8-byte entry so a lookup touches one line.
-// A stamp of kInelig marks a seed or a blocked vertex: it never becomes a visit, and an
-// atomic max with the current epoch both tests eligibility and claims the vertex.
-constexpr uint32_t kInelig = 0xFFFFFFFFu;
+// local id in that sample. Both halves live in one 8-byte entry so a lookup touches one line;
+// an atomic max with the current epoch claims the vertex.
 struct SlotEntry {
     uint32_t stamp;
     int32_t lid;
@@ -47,7 +50,8 @@ struct Workspace {
 struct DecreaseArgs {
     const int32_t *row_ptr;  // n + 1
     const uint4 *col4;       // ceil(m / 4) quads of edge targets (4 edges = 16 bytes)
-    const uint4 *thr4;       // ceil(m / 4) quads of live thresholds ceil(p * 2^24)
+    const uint4 *thr4;       // ceil(m / 4) quads of live thresholds ceil(p * 2^24), 0 for
+                             // edges into seeds and blocked vertices
     const int32_t *seeds;    // distinct seeds
     int32_t nseeds;
     int32_t n;
@@ -80,7 +84,9 @@ constexpr int kSmallWaves = 4;
 struct InstanceDesc {
     const int32_t *row_ptr;
     const uint4 *col4;
-    const uint4 *thr4;
+    uint4 *thr4;              // working thresholds (the batched argmax masks its winners)
+    const int32_t *in_ptr;    // in-edges of v: in_edge[in_ptr[v] .. in_ptr[v+1])
+    const int32_t *in_edge;   // edge ids
     uint32_t *inelig;         // bit v set: v is a seed or blocked (the argmax adds winners)
     const int32_t *seeds;
     unsigned long long *D;    // n decrease counters
@@ -116,24 +122,28 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t count, unsigned long l
 hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t stream);
 // Argmax of D over candidates (mode 0: bit of `bits` clear; mode 1: bit of `bits` set),
 // ties to the smallest id. Then: set the winner's bit in `inelig`, clear it in `cand`
-// (if non-null), store it in B[slot] and *out_x. *out_x = -1 when there is no candidate.
+// (if non-null), store it in B[slot] and *out_x, and give its in-edges threshold 0 in `thr`.
+// *out_x = -1 when there is no candidate.
 hipError_t launch_argmax_apply(const unsigned long long *D, const uint32_t *bits, int mode,
                                int32_t n, unsigned long long *part_d, int32_t *part_i,
                                int32_t parts, uint32_t *inelig, uint32_t *cand, int32_t *B,
-                               int32_t slot, int32_t *out_x, hipStream_t stream);
+                               int32_t slot, int32_t *out_x, uint32_t *thr,
+                               const int32_t *in_ptr, const int32_t *in_edge,
+                               hipStream_t stream);
 hipError_t launch_set_bit(uint32_t *bits, int32_t v, int value, hipStream_t stream);
-// Stamps of the slot maps: every vertex whose bit is set in `bits` becomes kInelig in all
-// slots; or the vertices of `list` (device) get `value`; or one vertex (host value, or the
-// device-resident id at `v_dev`, ignored when negative) gets `value`.
-hipError_t launch_mark_bitmap(SlotEntry *map, int32_t slots, int32_t n, const uint32_t *bits,
-                              hipStream_t stream);
-hipError_t launch_set_stamps(SlotEntry *map, int32_t slots, int32_t n, const int32_t *list,
-                             int32_t count, uint32_t value, hipStream_t stream);
-hipError_t launch_set_stamp(SlotEntry *map, int32_t slots, int32_t n, int32_t v,
-                            const int32_t *v_dev, uint32_t value, hipStream_t stream);
+// Thresholds of the in-edges of the vertices list[0..count) (device list), or of the one
+// vertex v (host value; or the device-resident id at v_dev when v_dev is non-null, ignored
+// when negative): set to 0 (restore == 0) or copied back from thr_orig (restore != 0).
+hipError_t launch_mask_list(uint32_t *thr, const uint32_t *thr_orig, const int32_t *in_ptr,
+                            const int32_t *in_edge, const int32_t *list, int32_t count,
+                            int restore, hipStream_t stream);
+hipError_t launch_mask_vertex(uint32_t *thr, const uint32_t *thr_orig, const int32_t *in_ptr,
+                              const int32_t *in_edge, int32_t v, const int32_t *v_dev,
+                              int restore, hipStream_t stream);
 // Batched greedy over instances inst[0..ninst): zero every instance's D; and per instance,
 // the AdvancedGreedy selection (argmax of D over vertices whose inelig bit is clear, ties to
-// the smallest id), applied as launch_argmax_apply does, with the winner in B[slot] and *x.
+// the smallest id), applied as launch_argmax_apply does, with the winner in B[slot] and *x
+// and its in-edges masked in the instance's thresholds.
 hipError_t launch_batch_zero(const InstanceDesc *inst, int32_t ninst, hipStream_t stream);
 hipError_t launch_batch_argmax(const InstanceDesc *inst, int32_t ninst, int32_t slot,
                                hipStream_t stream);

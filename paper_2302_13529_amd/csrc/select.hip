@@ -3,6 +3,8 @@
 // Ties go to the smallest vertex id, which makes the argmax order-independent.
 #include "imin_internal.h"
 
+#include <algorithm>
+
 namespace imin {
 namespace {
 
@@ -71,9 +73,18 @@ __global__ void argmax_partial_kernel(const unsigned long long *D, const uint32_
     }
 }
 
+// Threshold 0 for every in-edge of v, by the threads of one workgroup.
+__device__ __forceinline__ void mask_in_edges(uint32_t *thr, const int32_t *in_ptr,
+                                              const int32_t *in_edge, int v)
+{
+    for (int32_t k = in_ptr[v] + threadIdx.x; k < in_ptr[v + 1]; k += blockDim.x)
+        thr[in_edge[k]] = 0u;
+}
+
 __global__ void argmax_final_kernel(const unsigned long long *part_d, const int32_t *part_i,
                                     int32_t parts, uint32_t *inelig, uint32_t *cand, int32_t *B,
-                                    int32_t slot, int32_t *out_x)
+                                    int32_t slot, int32_t *out_x, uint32_t *thr,
+                                    const int32_t *in_ptr, const int32_t *in_edge)
 {
     unsigned long long bd = 0;
     int bi = -1;
@@ -87,6 +98,7 @@ __global__ void argmax_final_kernel(const unsigned long long *part_d, const int3
         }
         *out_x = bi;
     }
+    if (bi >= 0) mask_in_edges(thr, in_ptr, in_edge, bi);
 }
 
 __global__ void set_bit_kernel(uint32_t *bits, int32_t v, int value)
@@ -95,38 +107,31 @@ __global__ void set_bit_kernel(uint32_t *bits, int32_t v, int value)
     else bits[v >> 5] &= ~(1u << (v & 31));
 }
 
-__global__ void mark_bitmap_kernel(SlotEntry *map, int32_t slots, int32_t n, const uint32_t *bits)
+// In-edge thresholds of list[blockIdx.x ...] (grid-stride over the list): 0, or restored.
+__global__ void mask_list_kernel(uint32_t *thr, const uint32_t *thr_orig, const int32_t *in_ptr,
+                                 const int32_t *in_edge, const int32_t *list, int32_t count,
+                                 int restore)
 {
-    const int32_t words = (n + 31) / 32;
-    for (int32_t w = blockIdx.x * kSelBlock + threadIdx.x; w < words; w += gridDim.x * kSelBlock) {
-        uint32_t b = bits[w];
-        while (b) {
-            const int32_t v = w * 32 + __builtin_ctz(b);
-            b &= b - 1;
-            for (int32_t s = 0; s < slots; ++s) map[(size_t)s * n + v].stamp = kInelig;
+    for (int32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const int32_t v = list[i];
+        for (int32_t k = in_ptr[v] + threadIdx.x; k < in_ptr[v + 1]; k += kSelBlock) {
+            const int32_t e = in_edge[k];
+            thr[e] = restore ? thr_orig[e] : 0u;
         }
     }
 }
 
-__global__ void set_stamps_kernel(SlotEntry *map, int32_t slots, int32_t n, const int32_t *list,
-                                  int32_t count, uint32_t value)
-{
-    const int64_t total = (int64_t)slots * count;
-    for (int64_t i = blockIdx.x * (int64_t)kSelBlock + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * kSelBlock) {
-        const int32_t s = (int32_t)(i / count);
-        const int32_t v = list[i % count];
-        map[(size_t)s * n + v].stamp = value;
-    }
-}
-
-__global__ void set_stamp_kernel(SlotEntry *map, int32_t slots, int32_t n, int32_t v,
-                                 const int32_t *v_dev, uint32_t value)
+__global__ void mask_vertex_kernel(uint32_t *thr, const uint32_t *thr_orig, const int32_t *in_ptr,
+                                   const int32_t *in_edge, int32_t v, const int32_t *v_dev,
+                                   int restore)
 {
     const int32_t x = v_dev ? *v_dev : v;
     if (x < 0) return;
-    for (int32_t s = blockIdx.x * kSelBlock + threadIdx.x; s < slots; s += gridDim.x * kSelBlock)
-        map[(size_t)s * n + x].stamp = value;
+    for (int64_t k = in_ptr[x] + blockIdx.x * (int64_t)kSelBlock + threadIdx.x; k < in_ptr[x + 1];
+         k += (int64_t)gridDim.x * kSelBlock) {
+        const int32_t e = in_edge[k];
+        thr[e] = restore ? thr_orig[e] : 0u;
+    }
 }
 
 __global__ void batch_zero_kernel(const InstanceDesc *inst)
@@ -153,6 +158,7 @@ __global__ void batch_argmax_kernel(const InstanceDesc *inst, int32_t slot)
         }
         *I.x = bi;
     }
+    if (bi >= 0) mask_in_edges(reinterpret_cast<uint32_t *>(I.thr4), I.in_ptr, I.in_edge, bi);
 }
 
 int grid_for(int64_t count)
@@ -185,7 +191,9 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream
 hipError_t launch_argmax_apply(const unsigned long long *D, const uint32_t *bits, int mode,
                                int32_t n, unsigned long long *part_d, int32_t *part_i,
                                int32_t parts, uint32_t *inelig, uint32_t *cand, int32_t *B,
-                               int32_t slot, int32_t *out_x, hipStream_t stream)
+                               int32_t slot, int32_t *out_x, uint32_t *thr,
+                               const int32_t *in_ptr, const int32_t *in_edge,
+                               hipStream_t stream)
 {
     int g = grid_for(n);
     if (g > parts) g = parts;
@@ -194,34 +202,7 @@ hipError_t launch_argmax_apply(const unsigned long long *D, const uint32_t *bits
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(argmax_final_kernel, dim3(1), dim3(kSelBlock), 0, stream, part_d, part_i, g,
-                       inelig, cand, B, slot, out_x);
-    return hipGetLastError();
-}
-
-hipError_t launch_mark_bitmap(SlotEntry *map, int32_t slots, int32_t n, const uint32_t *bits,
-                              hipStream_t stream)
-{
-    if (slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mark_bitmap_kernel, dim3(grid_for((n + 31) / 32)), dim3(kSelBlock), 0,
-                       stream, map, slots, n, bits);
-    return hipGetLastError();
-}
-
-hipError_t launch_set_stamps(SlotEntry *map, int32_t slots, int32_t n, const int32_t *list,
-                             int32_t count, uint32_t value, hipStream_t stream)
-{
-    if (slots <= 0 || count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(set_stamps_kernel, dim3(grid_for((int64_t)slots * count)), dim3(kSelBlock),
-                       0, stream, map, slots, n, list, count, value);
-    return hipGetLastError();
-}
-
-hipError_t launch_set_stamp(SlotEntry *map, int32_t slots, int32_t n, int32_t v,
-                            const int32_t *v_dev, uint32_t value, hipStream_t stream)
-{
-    if (slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(set_stamp_kernel, dim3(grid_for(slots)), dim3(kSelBlock), 0, stream, map,
-                       slots, n, v, v_dev, value);
+                       inelig, cand, B, slot, out_x, thr, in_ptr, in_edge);
     return hipGetLastError();
 }
 
@@ -231,6 +212,24 @@ hipError_t launch_set_bit(uint32_t *bits, int32_t v, int value, hipStream_t stre
     return hipGetLastError();
 }
 
+hipError_t launch_mask_list(uint32_t *thr, const uint32_t *thr_orig, const int32_t *in_ptr,
+                            const int32_t *in_edge, const int32_t *list, int32_t count,
+                            int restore, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mask_list_kernel, dim3(std::min<int32_t>(count, 4096)), dim3(kSelBlock), 0,
+                       stream, thr, thr_orig, in_ptr, in_edge, list, count, restore);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_vertex(uint32_t *thr, const uint32_t *thr_orig, const int32_t *in_ptr,
+                              const int32_t *in_edge, int32_t v, const int32_t *v_dev,
+                              int restore, hipStream_t stream)
+{
+    hipLaunchKernelGGL(mask_vertex_kernel, dim3(16), dim3(kSelBlock), 0, stream, thr, thr_orig,
+                       in_ptr, in_edge, v, v_dev, restore);
+    return hipGetLastError();
+}
 
 hipError_t launch_batch_zero(const InstanceDesc *inst, int32_t ninst, hipStream_t stream)
 {

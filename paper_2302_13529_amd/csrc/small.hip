@@ -1,8 +1,9 @@
 // small.hip -- Algorithm 2 of arXiv 2302.13529 for samples that stay small: one wavefront per
 // sample, every per-sample array in LDS, no block barrier anywhere.
 //
-// A wave takes a (instance, sample) pair from a work counter spanning all instances of the
-// launch, so many graphs (the batched form) or one graph share the same launch. Per sample:
+// Waves take samples, a few consecutive ones at a time, from a work counter spanning all
+// instances of the launch, so many graphs (the batched form) or one graph share the same
+// launch. Per sample:
 //   * live edges are decided per 4-edge quad with the same Philox4x32-10 coin as the large
 //     kernel (Definition 4); lanes work on consecutive quads of the frontier;
 //   * reachability from the merged seed is a wave-synchronous BFS. The live edges a wave
@@ -11,9 +12,13 @@
 //   * dominators use the same Jacobi NCA raising from the BFS tree as the large kernel, and
 //     subtree sizes the same bottom-up pass over BFS levels (LDS atomics), with the sizes
 //     added into the instance's 64-bit counters D (Algorithm 2, Theorem 6).
+// Every sample of an instance expands the same seed rows, and only their coins differ; so a
+// wave keeps the seed quads of its current instance in registers (thresholds and targets)
+// and the seed level costs no memory traffic. Edges into seeds and blocked vertices have
+// threshold 0 during a call, so no sample ever finds them live.
 // A sample that reaches kSmallV - 1 vertices, keeps more than kSmallX extra edges, or meets a
-// frontier with more than the launch's quad limit is abandoned (nothing accumulated) and
-// listed for the large kernel, so results never depend on which path ran.
+// frontier chunk with more than the launch's quad limit is abandoned (nothing accumulated)
+// and listed for the large kernel, so results never depend on which path ran.
 #include "imin_internal.h"
 #include "philox.h"
 
@@ -23,6 +28,10 @@ namespace {
 constexpr int kSW = kSmallWaves;
 constexpr int kSmallBlock = kSW * 64;
 constexpr int kMaxSmallJacobiRounds = 4 * kSmallV;
+constexpr int kSeedSlots = 2;                      // cached seed quads per lane
+constexpr int kSeedCacheQuads = 64 * kSeedSlots;
+constexpr uint32_t kPickMin = 4;                   // samples per work-counter update:
+constexpr uint32_t kPickMax = 64;                  // a quarter of a fair share, within these
 
 struct WaveState {
     int gl[kSmallV];  // vertex id of each local id (local 0 is the merged seed: -1)
@@ -46,6 +55,35 @@ __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Inclusive prefix sum across the wave.
+__device__ __forceinline__ int wave_scan(int v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int quads_of(int e0, int e1)
+{
+    return (e1 > e0) ? (((e1 - 1) >> 2) - (e0 >> 2) + 1) : 0;
+}
+
+__device__ __forceinline__ int pick(uint4 v, int i)
+{
+    return (int)(i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w);
 }
 
 // Per-lane copy of the reached vertex ids: lane l holds local ids l, 64+l, 128+l, 192+l.
@@ -75,17 +113,15 @@ __device__ __forceinline__ int mirror_find(const Mirror &m, int c)
 }
 
 struct SampleCtx {
-    int nV, nX, L;
-    int ovf;
-    uint32_t live, scanned;
+    int nV, nX, L;     // uniform
+    int ovf;           // uniform
+    uint32_t live;     // per lane, summed at the end
+    uint32_t scanned;  // per lane, summed at the end
 };
 
-// Claim live edge src -> c for the sample (c, src uniform across the wave).
-__device__ __forceinline__ void claim(const InstanceDesc &I, WaveState &ws, Mirror &m,
-                                      SampleCtx &cx, int c, int src)
+// Claim live edge src -> c, whose target is known to be eligible (c, src uniform).
+__device__ __forceinline__ void claim(WaveState &ws, Mirror &m, SampleCtx &cx, int c, int src)
 {
-    if ((I.inelig[c >> 5] >> (c & 31)) & 1u) return;  // seeds and blocked vertices
-    ++cx.live;
     const int l = mirror_find(m, c);
     if (l < 0) {
         if (cx.nV >= kSmallV) {
@@ -109,6 +145,136 @@ __device__ __forceinline__ void claim(const InstanceDesc &I, WaveState &ws, Mirr
     }
 }
 
+// Claim every live edge the wave holds (per lane: `mask` over the targets in `col`, source
+// `src`), one at a time, lowest lane and bit first.
+__device__ __forceinline__ void claim_all(WaveState &ws, Mirror &m, SampleCtx &cx, uint32_t mask,
+                                          uint4 col, int src)
+{
+    const int lane = lane_id();
+    for (;;) {
+        const unsigned long long pend = __ballot(mask != 0);
+        if (!pend || cx.ovf) break;
+        const int leader = (int)__builtin_ctzll(pend);
+        const int myc = mask ? pick(col, __builtin_ctz(mask)) : 0;
+        const int c = __builtin_amdgcn_readfirstlane(__shfl(myc, leader, 64));
+        const int s = __builtin_amdgcn_readfirstlane(__shfl(src, leader, 64));
+        if (lane == leader) mask &= mask - 1;
+        claim(ws, m, cx, c, s);
+    }
+}
+
+// The current instance's seed level: quad p of the seed frontier sits in lane p % 64,
+// slot p / 64. vmask holds the edges of the quad that belong to the seed's row.
+struct SeedCache {
+    int quad[kSeedSlots];
+    uint4 thr[kSeedSlots];
+    uint4 col[kSeedSlots];
+    uint32_t vmask[kSeedSlots];
+    int total;         // cached quads (uniform); -1 when the seed rows do not fit
+    uint32_t scanned;  // out-edges of the seeds (uniform)
+};
+
+__device__ void build_seed_cache(const InstanceDesc &I, WaveState &ws, SeedCache &sc)
+{
+    const int lane = lane_id();
+    int total = 0;
+    uint32_t scanned = 0;
+    for (int base = 0; base < I.nseeds; base += 64) {
+        const int k = base + lane;
+        int e0 = 0, e1 = 0;
+        if (k < I.nseeds) {
+            const int v = I.seeds[k];
+            e0 = I.row_ptr[v];
+            e1 = I.row_ptr[v + 1];
+        }
+        total += (int)wave_sum((uint32_t)quads_of(e0, e1));
+        scanned += wave_sum((uint32_t)(e1 - e0));
+    }
+    sc.scanned = scanned;
+#pragma unroll
+    for (int s = 0; s < kSeedSlots; ++s) {
+        sc.quad[s] = 0;
+        sc.thr[s] = make_uint4(0, 0, 0, 0);
+        sc.col[s] = make_uint4(0, 0, 0, 0);
+        sc.vmask[s] = 0;
+    }
+    if (total > kSeedCacheQuads) {
+        sc.total = -1;
+        return;
+    }
+    sc.total = total;
+    int off = 0;
+    for (int base = 0; base < I.nseeds; base += 64) {
+        const int k = base + lane;
+        int e0 = 0, e1 = 0;
+        if (k < I.nseeds) {
+            const int v = I.seeds[k];
+            e0 = I.row_ptr[v];
+            e1 = I.row_ptr[v + 1];
+        }
+        const int nq = quads_of(e0, e1);
+        const int incl = wave_scan(nq);
+        const int ctot = __shfl(incl, 63, 64);
+        wave_sync();
+        ws.e0[lane] = e0;
+        ws.e1[lane] = e1;
+        ws.ex[lane] = incl - nq;
+        wave_sync();
+        const int cnt = min(64, I.nseeds - base);
+#pragma unroll
+        for (int s = 0; s < kSeedSlots; ++s) {
+            const int q = lane + 64 * s - off;
+            if (q >= 0 && q < ctot) {
+                int l = 0, h = cnt - 1;
+                while (l < h) {
+                    const int mid = (l + h + 1) >> 1;
+                    if (ws.ex[mid] <= q) l = mid;
+                    else h = mid - 1;
+                }
+                const int f0 = ws.e0[l], f1 = ws.e1[l];
+                const int quad = (f0 >> 2) + (q - ws.ex[l]);
+                const int eb = quad * 4;
+                uint32_t vm = 0;
+                for (int i = 0; i < 4; ++i)
+                    if (eb + i >= f0 && eb + i < f1) vm |= 1u << i;
+                sc.quad[s] = quad;
+                sc.vmask[s] = vm;
+            }
+        }
+        off += ctot;
+    }
+#pragma unroll
+    for (int s = 0; s < kSeedSlots; ++s) {
+        if (sc.vmask[s]) {
+            sc.thr[s] = I.thr4[sc.quad[s]];
+            sc.col[s] = I.col4[sc.quad[s]];
+        }
+    }
+}
+
+// Seed level of sample j from the cache.
+__device__ __forceinline__ void expand_seeds_cached(const SeedCache &sc, WaveState &ws, Mirror &m,
+                                                    SampleCtx &cx, uint32_t j, uint32_t key_lo,
+                                                    uint32_t key_hi)
+{
+    if (lane_id() == 0) cx.scanned += sc.scanned;
+#pragma unroll
+    for (int s = 0; s < kSeedSlots; ++s) {
+        if (64 * s >= sc.total || cx.ovf) break;
+        uint32_t mask = 0;
+        if (sc.vmask[s]) {
+            uint32_t w0, w1, w2, w3;
+            philox4x32_10((uint32_t)sc.quad[s], j, key_lo, key_hi, w0, w1, w2, w3);
+            const uint4 t = sc.thr[s];
+            mask = ((w0 >> 8) < t.x ? 1u : 0u) | ((w1 >> 8) < t.y ? 2u : 0u) |
+                   ((w2 >> 8) < t.z ? 4u : 0u) | ((w3 >> 8) < t.w ? 8u : 0u);
+            mask &= sc.vmask[s];
+        }
+        cx.live += (uint32_t)__builtin_popcount(mask);
+        claim_all(ws, m, cx, mask, sc.col[s], 0);
+    }
+}
+
 // Expand frontier [lo, hi): seeds of the instance (source = merged seed 0) or local ids.
 __device__ void expand_small(const InstanceDesc &I, WaveState &ws, Mirror &m, SampleCtx &cx,
                              bool from_seeds, int lo, int hi, uint32_t j, uint32_t key_lo,
@@ -118,20 +284,15 @@ __device__ void expand_small(const InstanceDesc &I, WaveState &ws, Mirror &m, Sa
     for (int base = lo; base < hi && !cx.ovf; base += 64) {
         wave_sync();
         const int k = base + lane;
-        int e0 = 0, e1 = 0, nq = 0;
+        int e0 = 0, e1 = 0;
         if (k < hi) {
             const int v = from_seeds ? I.seeds[k] : ws.gl[k];
             e0 = I.row_ptr[v];
             e1 = I.row_ptr[v + 1];
-            nq = (e1 > e0) ? (((e1 - 1) >> 2) - (e0 >> 2) + 1) : 0;
         }
-        cx.scanned += (uint32_t)(e1 - e0);  // per-lane share, reduced by the caller
-        int incl = nq;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int t = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += t;
-        }
+        const int nq = quads_of(e0, e1);
+        cx.scanned += (uint32_t)(e1 - e0);
+        const int incl = wave_scan(nq);
         const int total = __shfl(incl, 63, 64);
         if (total > quad_limit) {  // a heavy frontier: the large kernel does this better
             cx.ovf = 1;
@@ -156,26 +317,14 @@ __device__ void expand_small(const InstanceDesc &I, WaveState &ws, Mirror &m, Sa
                     else h = mid - 1;
                 }
                 const int quad = (ws.e0[l] >> 2) + (q - ws.ex[l]);
+                // both loads in flight at once: one memory round trip per level
                 const uint4 thr = I.thr4[quad];
+                col = I.col4[quad];
                 mask = live_mask(quad, j, key_lo, key_hi, ws.e0[l], ws.e1[l], thr);
-                if (mask) col = I.col4[quad];
                 src = from_seeds ? 0 : base + l;
             }
-            // claim the wave's live edges one at a time, lowest lane and bit first
-            for (;;) {
-                const unsigned long long pend = __ballot(mask != 0);
-                if (!pend || cx.ovf) break;
-                const int leader = (int)__builtin_ctzll(pend);
-                int myc = 0;
-                if (mask) {
-                    const int i = __builtin_ctz(mask);
-                    myc = (int)(i == 0 ? col.x : i == 1 ? col.y : i == 2 ? col.z : col.w);
-                }
-                const int c = __builtin_amdgcn_readfirstlane(__shfl(myc, leader, 64));
-                const int s = __builtin_amdgcn_readfirstlane(__shfl(src, leader, 64));
-                if (lane == leader) mask &= mask - 1;
-                claim(I, ws, m, cx, c, s);
-            }
+            cx.live += (uint32_t)__builtin_popcount(mask);
+            claim_all(ws, m, cx, mask, col, src);
         }
     }
 }
@@ -196,11 +345,123 @@ __device__ __forceinline__ int nca_small(const WaveState &ws, int x, int y, int 
     return x;
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+// Work counters of the current instance, kept per wave and added to the instance's
+// counters when the wave moves to another instance or ends.
+struct Tally {
+    unsigned long long samples, reached, scanned, live;
+};
+
+__device__ __forceinline__ void flush(const InstanceDesc &I, Tally &t)
 {
+    if (t.samples == 0) return;
+    if (lane_id() == 0) {
+        atomicAdd(&I.stats[0], t.samples);
+        atomicAdd(&I.stats[1], t.reached);
+        atomicAdd(&I.stats[2], t.scanned);
+        atomicAdd(&I.stats[3], t.live);
+        atomicAdd(&I.stats[5], t.samples);
+    }
+    t.samples = t.reached = t.scanned = t.live = 0;
+}
+
+// One sample: BFS, dominators, subtree sizes into D. Returns false when it must be handed
+// to the large kernel.
+__device__ bool run_sample(const SmallArgs &a, const InstanceDesc &I, const SeedCache &sc,
+                           WaveState &ws, uint32_t j, Tally &tally)
+{
+    const int lane = lane_id();
+    const unsigned long long key = (((unsigned long long)I.seed_hi << 32) | I.seed_lo) + a.round;
+    const uint32_t key_lo = (uint32_t)key, key_hi = (uint32_t)(key >> 32);
+    Mirror m;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    for (int r = 0; r < kSmallV / 64; ++r) m.g[r] = -1;
+    SampleCtx cx;
+    cx.nV = 1;
+    cx.nX = 0;
+    cx.L = 1;
+    cx.ovf = 0;
+    cx.live = 0;
+    cx.scanned = 0;
+    wave_sync();
+    if (lane == 0) {
+        ws.gl[0] = -1;
+        ws.pa[0] = 0;
+        ws.td[0] = 0;
+        ws.lvl[0] = 0;
+        ws.lvl[1] = 1;
+    }
+    wave_sync();
+    if (sc.total >= 0)
+        expand_seeds_cached(sc, ws, m, cx, j, key_lo, key_hi);
+    else
+        expand_small(I, ws, m, cx, true, 0, I.nseeds, j, key_lo, key_hi, a.quad_limit);
+    int flo = 1, fhi = cx.nV;
+    while (!cx.ovf && flo < fhi) {
+        if (lane == 0) ws.lvl[cx.L + 1] = fhi;
+        wave_sync();
+        expand_small(I, ws, m, cx, false, flo, fhi, j, key_lo, key_hi, a.quad_limit);
+        flo = fhi;
+        fhi = cx.nV;
+        ++cx.L;
+    }
+    if (cx.ovf) return false;
+    const int nV = cx.nV, nX = cx.nX, L = cx.L;
+    wave_sync();
+
+    // Dominator tree: Jacobi NCA steps over the extra edges (as in the workgroup kernel).
+    int bad = 0;
+    if (nX > 0) {
+        for (int round = 0;; ++round) {
+            for (int x = lane; x < nV; x += 64) ws.tn[x] = ws.td[x];
+            wave_sync();
+            for (int e = lane; e < nX; e += 64) {
+                const int2 ed = ws.extra[e];
+                const int tv = ws.td[ed.y];
+                const int m1 = nca_small(ws, tv, ed.x, bad);
+                const int m2 = nca_small(ws, tv, ws.pa[ed.y], bad);
+                const int mm = min(m1, m2);
+                if (mm < tv) atomicMin(&ws.tn[ed.y], mm);
+            }
+            wave_sync();
+            int changed = 0;
+            for (int x = lane; x < nV; x += 64) {
+                const int nt = ws.tn[x];
+                if (nt != ws.td[x]) {
+                    ws.td[x] = nt;
+                    changed = 1;
+                }
+            }
+            wave_sync();
+            if (!__any(changed) || __any(bad)) break;
+            if (round >= kMaxSmallJacobiRounds) {
+                bad = 1;
+                break;
+            }
+        }
+    }
+    if (__any(bad)) {
+        if (lane == 0) atomicOr(a.error, 2u);
+        return true;  // never expected; reported through the error flag
+    }
+
+    // Subtree sizes, deepest BFS level first, accumulated into the instance's D.
+    for (int x = lane; x < nV; x += 64) ws.tn[x] = 1;
+    wave_sync();
+    for (int l = L - 1; l >= 1; --l) {
+        const int b0 = ws.lvl[l], b1 = ws.lvl[l + 1];
+        for (int x = b0 + lane; x < b1; x += 64) {
+            const int c = ws.tn[x];
+            const int p = ws.td[x];
+            if (p != 0) atomicAdd(&ws.tn[p], c);
+            atomicAdd(&I.D[ws.gl[x]], (unsigned long long)c);
+        }
+        wave_sync();
+    }
+    tally.samples += 1;
+    tally.reached += (unsigned long long)(nV - 1);
+    tally.scanned += wave_sum(cx.scanned);
+    tally.live += wave_sum(cx.live);
+    return true;
 }
 
 __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a)
@@ -209,123 +470,53 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
     const int lane = lane_id();
     WaveState &ws = smem.w[threadIdx.x >> 6];
 
+    int cur = -1;
+    InstanceDesc I{};
+    uint32_t cur_lo = 0, cur_hi = 0;
+    SeedCache sc;
+    sc.total = -1;
+    Tally tally{0, 0, 0, 0};
+    const uint32_t nwaves = gridDim.x * kSW;
     for (;;) {
-        uint32_t idx = 0;
-        if (lane == 0) idx = atomicAdd(a.next, 1u);
-        idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
-        if (idx >= a.total) break;
-        // instance of this sample: the last one whose first sample index is <= idx
-        int lo = 0, hi = a.ninst - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.inst[mid].sample_base <= idx) lo = mid;
-            else hi = mid - 1;
-        }
-        lo = __builtin_amdgcn_readfirstlane(lo);
-        const InstanceDesc &I = a.inst[lo];
-        const uint32_t j = idx - I.sample_base;
-        const unsigned long long key =
-            (((unsigned long long)I.seed_hi << 32) | I.seed_lo) + a.round;
-        const uint32_t key_lo = (uint32_t)key, key_hi = (uint32_t)(key >> 32);
-
-        Mirror m;
-#pragma unroll
-        for (int r = 0; r < kSmallV / 64; ++r) m.g[r] = -1;
-        SampleCtx cx;
-        cx.nV = 1;
-        cx.nX = 0;
-        cx.L = 1;
-        cx.ovf = 0;
-        cx.live = 0;
-        cx.scanned = 0;
-        wave_sync();
+        // Guided self-scheduling: runs of consecutive samples (one instance, one seed cache)
+        // that shrink as the launch drains, so the waves finish together.
+        uint32_t first = 0, want = kPickMin;
         if (lane == 0) {
-            ws.gl[0] = -1;
-            ws.pa[0] = 0;
-            ws.td[0] = 0;
-            ws.lvl[0] = 0;
-            ws.lvl[1] = 1;
+            const uint32_t seen =
+                __hip_atomic_load(a.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (seen < a.total)
+                want = max(kPickMin, min(kPickMax, (a.total - seen) / (4u * nwaves)));
+            first = atomicAdd(a.next, want);
         }
-        wave_sync();
-        expand_small(I, ws, m, cx, true, 0, I.nseeds, j, key_lo, key_hi, a.quad_limit);
-        int flo = 1, fhi = cx.nV;
-        while (!cx.ovf && flo < fhi) {
-            if (lane == 0) ws.lvl[cx.L + 1] = fhi;
-            wave_sync();
-            expand_small(I, ws, m, cx, false, flo, fhi, j, key_lo, key_hi, a.quad_limit);
-            flo = fhi;
-            fhi = cx.nV;
-            ++cx.L;
-        }
-        if (cx.ovf) {
-            if (lane == 0) {
+        first = __builtin_amdgcn_readfirstlane(__shfl(first, 0, 64));
+        want = __builtin_amdgcn_readfirstlane(__shfl(want, 0, 64));
+        if (first >= a.total) break;
+        const uint32_t last = min(first + want, a.total);
+        for (uint32_t idx = first; idx < last; ++idx) {
+            if (cur < 0 || idx < cur_lo || idx >= cur_hi) {
+                if (cur >= 0) flush(I, tally);
+                // the last instance whose first sample index is <= idx
+                int lo = 0, hi = a.ninst - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (a.inst[mid].sample_base <= idx) lo = mid;
+                    else hi = mid - 1;
+                }
+                cur = __builtin_amdgcn_readfirstlane(lo);
+                I = a.inst[cur];
+                cur_lo = I.sample_base;
+                cur_hi = I.sample_base + I.theta;
+                build_seed_cache(I, ws, sc);
+            }
+            const uint32_t j = idx - cur_lo;
+            if (!run_sample(a, I, sc, ws, j, tally) && lane == 0) {
                 const uint32_t pos = atomicAdd(a.spill_count, 1u);
-                if (a.spill_inst) a.spill_inst[pos] = (uint32_t)lo;
+                if (a.spill_inst) a.spill_inst[pos] = (uint32_t)cur;
                 a.spill_j[pos] = j;
             }
-            continue;
-        }
-        const int nV = cx.nV, nX = cx.nX, L = cx.L;
-        wave_sync();
-
-        // Dominator tree: Jacobi NCA steps over the extra edges (see decrease.hip).
-        int bad = 0;
-        if (nX > 0) {
-            for (int round = 0;; ++round) {
-                for (int x = lane; x < nV; x += 64) ws.tn[x] = ws.td[x];
-                wave_sync();
-                for (int e = lane; e < nX; e += 64) {
-                    const int2 ed = ws.extra[e];
-                    const int tv = ws.td[ed.y];
-                    const int m1 = nca_small(ws, tv, ed.x, bad);
-                    const int m2 = nca_small(ws, tv, ws.pa[ed.y], bad);
-                    const int mm = min(m1, m2);
-                    if (mm < tv) atomicMin(&ws.tn[ed.y], mm);
-                }
-                wave_sync();
-                int changed = 0;
-                for (int x = lane; x < nV; x += 64) {
-                    const int nt = ws.tn[x];
-                    if (nt != ws.td[x]) {
-                        ws.td[x] = nt;
-                        changed = 1;
-                    }
-                }
-                wave_sync();
-                if (!__any(changed) || __any(bad)) break;
-                if (round >= kMaxSmallJacobiRounds) {
-                    bad = 1;
-                    break;
-                }
-            }
-        }
-        if (__any(bad)) {
-            if (lane == 0) atomicOr(a.error, 2u);
-            continue;
-        }
-
-        // Subtree sizes, deepest BFS level first, accumulated into the instance's D.
-        for (int x = lane; x < nV; x += 64) ws.tn[x] = 1;
-        wave_sync();
-        for (int l = L - 1; l >= 1; --l) {
-            const int b0 = ws.lvl[l], b1 = ws.lvl[l + 1];
-            for (int x = b0 + lane; x < b1; x += 64) {
-                const int c = ws.tn[x];
-                const int p = ws.td[x];
-                if (p != 0) atomicAdd(&ws.tn[p], c);
-                atomicAdd(&I.D[ws.gl[x]], (unsigned long long)c);
-            }
-            wave_sync();
-        }
-        const uint32_t scanned = wave_sum(cx.scanned);
-        if (lane == 0) {
-            atomicAdd(&I.stats[0], 1ull);
-            atomicAdd(&I.stats[1], (unsigned long long)(nV - 1));
-            atomicAdd(&I.stats[2], (unsigned long long)scanned);
-            atomicAdd(&I.stats[3], (unsigned long long)cx.live);
-            atomicAdd(&I.stats[5], 1ull);
         }
     }
+    if (cur >= 0) flush(I, tally);
 }
 
 }  // namespace

@@ -106,13 +106,22 @@ def test_batch_equals_plain_and_oracle(gpu, batch16):
         assert st["live_edges"] == so["live_edges"], i
         Bp, sp = g.greedy(t.seeds, b, th, t.seed, gpu.IMIN_AG)
         assert list(Bp) == list(B), i
+    for wpc, ql in ((4, 0), (8, 1), (32, 64)):
+        case(f"batched AG, waves_per_cu={wpc} quad_limit={ql}")
+        res2 = gpu.imin_greedy_batch(probs, gpu.IMIN_AG, wpc, ql)
+        for (B, st), (B2, st2) in zip(res, res2):
+            assert list(B) == list(B2)
+            assert st["reached"] == st2["reached"] and st["live_edges"] == st2["live_edges"]
+        if ql == 1:  # most seed frontiers are handed over at once
+            assert sum(st2["wave_samples"] for _, st2 in res2) < \
+                sum(st2["samples"] for _, st2 in res2)
     for g in graphs:
         g.close()
 
 
 def test_batch_with_handed_over_samples_and_existing_scratch(gpu, batch16):
     """Instances whose samples outgrow the wave kernel, one of whose graphs already holds
-    workgroup scratch (and stale seed stamps) from an earlier plain call."""
+    workgroup scratch and the masked thresholds of other seeds from an earlier plain call."""
     t0, t1 = batch16[0], batch16[1]
     prp, pc, pp = _path_graph()
     drp, dc, dp = _dense_graph()
@@ -120,7 +129,7 @@ def test_batch_with_handed_over_samples_and_existing_scratch(gpu, batch16):
     gdense = gpu.Graph(drp, dc, dp)
     g0 = gpu.Graph(t0.row_ptr, t0.col, t0.prob)
     g1 = gpu.Graph(t1.row_ptr, t1.col, t1.prob)
-    case("plain call on the dense graph with other seeds, leaving scratch and stamps")
+    case("plain call on the dense graph with other seeds, leaving scratch and masks")
     gdense.greedy([5, 6], 2, 30, 9, gpu.IMIN_AG)
     probs = [(gpath.handle, [0], 4, 60, 1), (gdense.handle, [0], 3, 70, 2),
              (g0.handle, t0.seeds, 3, 200, 3), (g1.handle, t1.seeds, 2, 300, 4)]
