@@ -278,17 +278,9 @@ int seed_setup(imin_graph *g, const int32_t *S, int32_t nS, std::vector<int32_t>
     return IMIN_OK;
 }
 
-int upload_call_state(imin_graph *g, const std::vector<int32_t> &seeds,
-                      const std::vector<uint32_t> &inelig, uint64_t seed, uint32_t theta)
+// The graph as one instance of a wave-kernel launch (host copy in g->h_inst).
+void describe(imin_graph *g, int32_t nseeds, uint64_t seed, uint32_t theta)
 {
-    if (!ok(hipMemcpyAsync(g->d_seeds, seeds.data(), seeds.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, g->stream)) ||
-        !ok(hipMemcpyAsync(g->d_inelig, inelig.data(), inelig.size() * sizeof(uint32_t),
-                           hipMemcpyHostToDevice, g->stream)))
-        return IMIN_EDEVICE;
-    if (!ok(imin::launch_fill_u64(g->d_stats, kStats, 0, g->stream)) ||
-        !ok(imin::launch_fill_u32(g->d_ctrl, 4, 0, g->stream)))
-        return IMIN_EDEVICE;
     imin::InstanceDesc &I = g->h_inst;
     I.row_ptr = g->d_row_ptr;
     I.col4 = g->d_col4;
@@ -301,12 +293,29 @@ int upload_call_state(imin_graph *g, const std::vector<int32_t> &seeds,
     I.stats = g->d_stats;
     I.B = g->d_B;
     I.x = g->d_x;
-    I.nseeds = (int32_t)seeds.size();
+    I.thr_orig = g->d_thr_orig;
+    I.ctrl = g->d_ctrl;
+    I.nseeds = nseeds;
     I.n = g->n;
+    I.nquads = (int32_t)std::max<int64_t>(((int64_t)g->m + 3) / 4, 1);
     I.seed_lo = (uint32_t)seed;
     I.seed_hi = (uint32_t)(seed >> 32);
     I.theta = theta;
     I.sample_base = 0;
+}
+
+int upload_call_state(imin_graph *g, const std::vector<int32_t> &seeds,
+                      const std::vector<uint32_t> &inelig, uint64_t seed, uint32_t theta)
+{
+    if (!ok(hipMemcpyAsync(g->d_seeds, seeds.data(), seeds.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, g->stream)) ||
+        !ok(hipMemcpyAsync(g->d_inelig, inelig.data(), inelig.size() * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, g->stream)))
+        return IMIN_EDEVICE;
+    if (!ok(imin::launch_fill_u64(g->d_stats, kStats, 0, g->stream)) ||
+        !ok(imin::launch_fill_u32(g->d_ctrl, 4, 0, g->stream)))
+        return IMIN_EDEVICE;
+    describe(g, (int32_t)seeds.size(), seed, theta);
     if (!ok(hipMemcpyAsync(g->d_inst, &g->h_inst, sizeof(imin::InstanceDesc),
                            hipMemcpyHostToDevice, g->stream)))
         return IMIN_EDEVICE;
@@ -944,7 +953,10 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, int32_t wave
     imin_graph *g0 = inst[0].g;
     g0->kev_used = 0;
     if (!ok(hipEventRecord(g0->ev0, bs))) return IMIN_EDEVICE;
+    // Call state of every instance, staged in one buffer and put in place by one kernel.
     std::vector<imin::InstanceDesc> table((size_t)count);
+    std::vector<imin::BatchStage> stages((size_t)count);
+    std::vector<int32_t> stage, rounds((size_t)count);
     std::vector<uint32_t> prefix((size_t)count + 1, 0u);
     int32_t max_rounds = 0;
     for (int32_t i = 0; i < count; ++i) {
@@ -956,22 +968,50 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, int32_t wave
         if (rc) return rc;
         rc = ensure_B(g, it.rounds);
         if (rc) return rc;
-        rc = upload_call_state(g, it.seeds, it.inelig, it.in->seed, it.in->theta);
-        if (rc) return rc;
+        describe(g, (int32_t)it.seeds.size(), it.in->seed, it.in->theta);
         table[(size_t)i] = g->h_inst;
         table[(size_t)i].sample_base = prefix[(size_t)i];
         prefix[(size_t)i + 1] = prefix[(size_t)i] + it.in->theta;
+        rounds[(size_t)i] = it.rounds;
         max_rounds = std::max(max_rounds, it.rounds);
+        imin::BatchStage &S = stages[(size_t)i];
+        S.seeds = (int64_t)stage.size();
+        stage.insert(stage.end(), it.seeds.begin(), it.seeds.end());
+        S.bits = (int64_t)stage.size();
+        S.words = (int32_t)it.inelig.size();
+        for (uint32_t w : it.inelig) stage.push_back((int32_t)w);
+        S.prev = (int64_t)stage.size();
+        S.nprev = g->mask_known ? (int32_t)g->masked.size() : -1;
+        if (g->mask_known) stage.insert(stage.end(), g->masked.begin(), g->masked.end());
+        g->mask_known = false;
+        g->masked.clear();
+        for (int32_t v = 0; v < g->n; ++v)
+            if ((it.inelig[(size_t)v >> 5] >> (v & 31)) & 1u) g->masked.push_back(v);
+        S.now = (int64_t)stage.size();
+        S.nnow = (int32_t)g->masked.size();
+        stage.insert(stage.end(), g->masked.begin(), g->masked.end());
     }
+    const int32_t stride = 13 + std::max(max_rounds, 1);
     DeviceBuf<imin::InstanceDesc> d_table;
+    DeviceBuf<imin::BatchStage> d_stages;
+    DeviceBuf<int32_t> d_stage, d_rounds, d_out;
     DeviceBuf<uint32_t> d_si, d_sj, d_ctrl;
-    if (!d_table.alloc((size_t)count) || !d_si.alloc(theta_sum) || !d_sj.alloc(theta_sum) ||
-        !d_ctrl.alloc(3)) {
+    if (!d_table.alloc((size_t)count) || !d_stages.alloc((size_t)count) ||
+        !d_stage.alloc(stage.size()) || !d_rounds.alloc((size_t)count) ||
+        !d_out.alloc((size_t)count * stride) || !d_si.alloc(theta_sum) ||
+        !d_sj.alloc(theta_sum) || !d_ctrl.alloc(3)) {
         (void)hipGetLastError();
         return IMIN_ENOMEM;
     }
     if (!ok(hipMemcpyAsync(d_table.p, table.data(), table.size() * sizeof(imin::InstanceDesc),
                            hipMemcpyHostToDevice, bs)) ||
+        !ok(hipMemcpyAsync(d_stages.p, stages.data(), stages.size() * sizeof(imin::BatchStage),
+                           hipMemcpyHostToDevice, bs)) ||
+        !ok(hipMemcpyAsync(d_stage.p, stage.data(), stage.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, bs)) ||
+        !ok(hipMemcpyAsync(d_rounds.p, rounds.data(), rounds.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, bs)) ||
+        !ok(imin::launch_batch_setup(d_table.p, d_stages.p, d_stage.p, count, bs)) ||
         !ok(imin::launch_fill_u32(d_ctrl.p, 3, 0, bs)))
         return IMIN_EDEVICE;
     int rc = IMIN_OK;
@@ -1047,26 +1087,27 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, int32_t wave
         }
         if (!ok(imin::launch_batch_argmax(d_table.p, active, r, bs))) return IMIN_EDEVICE;
     }
-    // Results: every graph's blocker slots, counters and error flag, then one wait.
-    std::vector<std::vector<int32_t>> B((size_t)count);
-    std::vector<std::array<unsigned long long, kStats>> st((size_t)count);
-    std::vector<std::array<uint32_t, 4>> ctrl((size_t)count);
+    // Results: every graph's blocker slots, counters and error flag, gathered into one
+    // buffer, then one copy and one wait.
+    std::vector<int32_t> out((size_t)count * stride);
     uint32_t berr[3] = {0, 0, 0};
-    for (int32_t i = 0; i < count; ++i) {
-        BatchItem &it = items[(size_t)i];
-        B[(size_t)i].assign((size_t)it.rounds, -1);
-        if ((it.rounds > 0 &&
-             !ok(hipMemcpyAsync(B[(size_t)i].data(), it.g->d_B, (size_t)it.rounds * sizeof(int32_t),
-                                hipMemcpyDeviceToHost, bs))) ||
-            !ok(hipMemcpyAsync(st[(size_t)i].data(), it.g->d_stats,
-                               kStats * sizeof(unsigned long long), hipMemcpyDeviceToHost, bs)) ||
-            !ok(hipMemcpyAsync(ctrl[(size_t)i].data(), it.g->d_ctrl, 4 * sizeof(uint32_t),
-                               hipMemcpyDeviceToHost, bs)))
-            return IMIN_EDEVICE;
-    }
-    if (!ok(hipMemcpyAsync(berr, d_ctrl.p, sizeof(berr), hipMemcpyDeviceToHost, bs)) ||
+    if (!ok(imin::launch_batch_gather(d_table.p, d_rounds.p, d_out.p, stride, count, bs)) ||
+        !ok(hipMemcpyAsync(out.data(), d_out.p, out.size() * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, bs)) ||
+        !ok(hipMemcpyAsync(berr, d_ctrl.p, sizeof(berr), hipMemcpyDeviceToHost, bs)) ||
         !ok(hipEventRecord(g0->ev1, bs)) || !ok(hipEventSynchronize(g0->ev1)))
         return IMIN_EDEVICE;
+    std::vector<std::vector<int32_t>> B((size_t)count);
+    std::vector<std::array<unsigned long long, kStats>> st((size_t)count);
+    std::vector<uint32_t> err((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        const int32_t *o = out.data() + (size_t)i * stride;
+        for (int k = 0; k < kStats; ++k)
+            st[(size_t)i][k] = (unsigned long long)(uint32_t)o[2 * k] |
+                               ((unsigned long long)(uint32_t)o[2 * k + 1] << 32);
+        err[(size_t)i] = (uint32_t)o[12];
+        B[(size_t)i].assign(o + 13, o + 13 + items[(size_t)i].rounds);
+    }
     if (berr[2] != 0) return IMIN_EDEVICE;
     float total_ms = 0.0f;
     if (!ok(hipEventElapsedTime(&total_ms, g0->ev0, g0->ev1))) return IMIN_EDEVICE;
@@ -1077,7 +1118,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, int32_t wave
         kms += x;
     }
     for (int32_t i = 0; i < count; ++i) {
-        if (ctrl[(size_t)i][3] != 0) return IMIN_EDEVICE;
+        if (err[(size_t)i] != 0) return IMIN_EDEVICE;
         for (int32_t v : B[(size_t)i])
             if (v < 0) return IMIN_EDEVICE;
     }

@@ -93,8 +93,11 @@ struct InstanceDesc {
     unsigned long long *stats; // samples, reached, edges scanned, live edges, -, wave samples
     int32_t *B;               // blocker slots (batched greedy)
     int32_t *x;               // the last round's winner (batched greedy)
+    const uint4 *thr_orig;    // thresholds as created (batched set-up restores from them)
+    uint32_t *ctrl;           // the graph's 4 control words of the workgroup kernel
     int32_t nseeds;
     int32_t n;
+    int32_t nquads;           // quads of thr4
     uint32_t seed_lo, seed_hi;
     uint32_t theta;
     uint32_t sample_base;
@@ -145,6 +148,23 @@ hipError_t launch_mask_vertex(uint32_t *thr, const uint32_t *thr_orig, const int
 // the smallest id), applied as launch_argmax_apply does, with the winner in B[slot] and *x
 // and its in-edges masked in the instance's thresholds.
 hipError_t launch_batch_zero(const InstanceDesc *inst, int32_t ninst, hipStream_t stream);
+
+// Per-instance call state of a batched call, staged in one device buffer `stage`:
+// seeds at [seeds, seeds + nseeds), the seed/blocked bitmap at [bits, bits + words), the
+// vertices the previous call left masked at [prev, prev + nprev) (nprev < 0: restore every
+// threshold), and the vertices to mask now at [now, now + nnow).
+struct BatchStage {
+    int64_t seeds, bits, prev, now;
+    int32_t words, nprev, nnow, pad;
+};
+// One workgroup per instance: copy seeds and bitmap into place, clear the counters and
+// control words, restore the previous masks, then mask the new ones.
+hipError_t launch_batch_setup(const InstanceDesc *inst, const BatchStage *st,
+                              const int32_t *stage, int32_t ninst, hipStream_t stream);
+// One workgroup per instance: B[0..rounds[i]), the 6 counters and control word 3 of
+// instance i into out + i * stride (int32 words; counters as pairs of words).
+hipError_t launch_batch_gather(const InstanceDesc *inst, const int32_t *rounds, int32_t *out,
+                               int32_t stride, int32_t ninst, hipStream_t stream);
 hipError_t launch_batch_argmax(const InstanceDesc *inst, int32_t ninst, int32_t slot,
                                hipStream_t stream);
 

@@ -161,6 +161,46 @@ __global__ void batch_argmax_kernel(const InstanceDesc *inst, int32_t slot)
     if (bi >= 0) mask_in_edges(reinterpret_cast<uint32_t *>(I.thr4), I.in_ptr, I.in_edge, bi);
 }
 
+__global__ void batch_setup_kernel(const InstanceDesc *inst, const BatchStage *st,
+                                   const int32_t *stage)
+{
+    const InstanceDesc &I = inst[blockIdx.x];
+    const BatchStage &S = st[blockIdx.x];
+    int32_t *seeds = const_cast<int32_t *>(I.seeds);
+    for (int32_t k = threadIdx.x; k < I.nseeds; k += kSelBlock) seeds[k] = stage[S.seeds + k];
+    for (int32_t k = threadIdx.x; k < S.words; k += kSelBlock)
+        I.inelig[k] = (uint32_t)stage[S.bits + k];
+    if (threadIdx.x < 6) I.stats[threadIdx.x] = 0ull;
+    if (threadIdx.x < 4) I.ctrl[threadIdx.x] = 0u;
+    uint32_t *thr = reinterpret_cast<uint32_t *>(I.thr4);
+    const uint32_t *orig = reinterpret_cast<const uint32_t *>(I.thr_orig);
+    if (S.nprev < 0) {
+        for (int64_t e = threadIdx.x; e < (int64_t)I.nquads * 4; e += kSelBlock) thr[e] = orig[e];
+    } else {
+        for (int32_t i = 0; i < S.nprev; ++i) {
+            const int32_t v = stage[S.prev + i];
+            for (int32_t k = I.in_ptr[v] + threadIdx.x; k < I.in_ptr[v + 1]; k += kSelBlock)
+                thr[I.in_edge[k]] = orig[I.in_edge[k]];
+        }
+    }
+    __syncthreads();
+    for (int32_t i = 0; i < S.nnow; ++i) mask_in_edges(thr, I.in_ptr, I.in_edge, stage[S.now + i]);
+}
+
+__global__ void batch_gather_kernel(const InstanceDesc *inst, const int32_t *rounds, int32_t *out,
+                                    int32_t stride)
+{
+    const InstanceDesc &I = inst[blockIdx.x];
+    int32_t *o = out + (int64_t)blockIdx.x * stride;
+    for (int32_t k = threadIdx.x; k < rounds[blockIdx.x]; k += kSelBlock) o[13 + k] = I.B[k];
+    if (threadIdx.x < 6) {
+        const unsigned long long v = I.stats[threadIdx.x];
+        o[2 * threadIdx.x] = (int32_t)(uint32_t)v;
+        o[2 * threadIdx.x + 1] = (int32_t)(uint32_t)(v >> 32);
+    }
+    if (threadIdx.x == 0) o[12] = (int32_t)I.ctrl[3];
+}
+
 int grid_for(int64_t count)
 {
     int64_t g = (count + kSelBlock - 1) / kSelBlock;
@@ -243,6 +283,24 @@ hipError_t launch_batch_argmax(const InstanceDesc *inst, int32_t ninst, int32_t 
 {
     if (ninst <= 0) return hipSuccess;
     hipLaunchKernelGGL(batch_argmax_kernel, dim3(ninst), dim3(kSelBlock), 0, stream, inst, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_setup(const InstanceDesc *inst, const BatchStage *st,
+                              const int32_t *stage, int32_t ninst, hipStream_t stream)
+{
+    if (ninst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_setup_kernel, dim3(ninst), dim3(kSelBlock), 0, stream, inst, st,
+                       stage);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_gather(const InstanceDesc *inst, const int32_t *rounds, int32_t *out,
+                               int32_t stride, int32_t ninst, hipStream_t stream)
+{
+    if (ninst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_gather_kernel, dim3(ninst), dim3(kSelBlock), 0, stream, inst, rounds,
+                       out, stride);
     return hipGetLastError();
 }
 
