@@ -78,12 +78,20 @@ def bench_batched(args) -> dict:
     insts = gg.batched_instances()
     graphs = [binding.Graph(t.row_ptr, t.col, t.prob) for t in insts]
     probs = [(g.handle, t.seeds, t.b, t.theta, t.seed) for g, t in zip(graphs, insts)]
-    wpc, ql = args.waves_per_cu, args.quad_limit
+    from paper_2302_13529_amd import autotune
+    launch = dict(waves_per_cu=args.waves_per_cu, quad_limit=args.quad_limit,
+                  pick_div=args.pick_div)
+    tuned_key = None
+    if not any(launch.values()):
+        print("[bench] launch shape from the autotuner", file=sys.stderr, flush=True)
+        tuned_key, tuned = autotune.tuned_batch_launch(insts, probs, tune_if_missing=args.tune)
+        if tuned:
+            launch = tuned
     print(f"[bench] warmup: plain and batched, {args.warmup} each", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         for g, t in zip(graphs, insts):
             g.greedy(t.seeds, t.b, t.theta, t.seed, binding.IMIN_AG)
-        binding.imin_greedy_batch(probs, binding.IMIN_AG, wpc, ql)
+        binding.imin_greedy_batch(probs, binding.IMIN_AG, launch)
     torch.cuda.synchronize()
     print(f"[bench] plain: {len(insts)} greedy calls", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -95,7 +103,7 @@ def bench_batched(args) -> dict:
     print(f"[bench] batched: {args.steps} calls", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        res = binding.imin_greedy_batch(probs, binding.IMIN_AG, wpc, ql)
+        res = binding.imin_greedy_batch(probs, binding.IMIN_AG, launch)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     identical = all(list(a[0]) == list(b[0]) for a, b in zip(plain, res))
@@ -122,7 +130,7 @@ def bench_batched(args) -> dict:
         "config": {"workload": "chunglu_batch256_tr", "instances": len(insts),
                    "theta": insts[0].theta, "b": insts[0].b,
                    "step": "one batched AdvancedGreedy call over all instances",
-                   "parallelism": "none"},
+                   "parallelism": "none", "launch": launch, "tuned_key": tuned_key},
         "plain_value": plain_samples / plain_s,
         "speedup_vs_plain": (samples / dt) / (plain_samples / plain_s),
         "identical_to_plain": identical,
@@ -166,6 +174,9 @@ def main() -> int:
     ap.add_argument("--workload", choices=["rmat22", "batched"], default="rmat22")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--quad-limit", type=int, default=0)
+    ap.add_argument("--pick-div", type=int, default=0)
+    ap.add_argument("--tune", action="store_true",
+                    help="batched workload: tune the launch shape if no cached entry exists")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "

@@ -147,20 +147,35 @@ IMIN_API int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b,
 IMIN_API int imin_set_launch(imin_graph *g, int32_t slots, int64_t extra_cap);
 
 /*
- * imin_set_small -- launch policy of the one-wave-per-sample kernel for later calls on g.
- * Every sample first runs in one wavefront with LDS-resident state; a sample that reaches
- * more than 255 vertices, keeps more than 256 non-tree live edges, or meets a 64-vertex
- * frontier chunk with more than quad_limit 4-edge quads is left, with nothing accumulated,
- * to the one-workgroup-per-sample kernel in the same call.
- *   enable        -1 automatic (the default: on, and switched off for g once fewer than
- *                 half of a round's samples finish in the wave kernel), 0 off, 1 on.
- *   waves_per_cu  resident waves per compute unit for the wave kernel (0: default 20).
- *   quad_limit    as above (0: default 2048).
- * Results never depend on these values. Errors: IMIN_EINVAL for NULL g, enable outside
- * [-1, 1], or negative sizes.
+ * Launch shape of the one-wave-per-sample kernel. Every field 0 means "default"; the values
+ * change speed only, never results.
+ *   waves_per_cu  waves launched per compute unit (default 20; the kernel is persistent,
+ *                 so waves beyond what fits on a unit start as others finish).
+ *   quad_limit    a 64-vertex frontier chunk with more 4-edge quads than this is left to
+ *                 the workgroup kernel (default 2048). The seed level is exempt when its
+ *                 rows fit the kernel's 128-quad seed cache.
+ *   pick_div      waves take runs of consecutive samples of about a 1/pick_div share of
+ *                 what remains per wave, between 4 and 64 samples (default 4).
  */
-IMIN_API int imin_set_small(imin_graph *g, int32_t enable, int32_t waves_per_cu,
-                            int32_t quad_limit);
+typedef struct {
+    int32_t waves_per_cu;
+    int32_t quad_limit;
+    int32_t pick_div;
+} imin_launch;
+
+/*
+ * imin_set_small -- policy of the one-wave-per-sample kernel for later calls on g.
+ * Every sample first runs in one wavefront with LDS-resident state; a sample that reaches
+ * more than 255 vertices, keeps more than 256 non-tree live edges, or meets a frontier
+ * chunk over the quad limit is left, with nothing accumulated, to the one-workgroup-per-
+ * sample kernel in the same call.
+ *   enable  -1 automatic (the default: on, and switched off for g once fewer than half of
+ *           a round's samples finish in the wave kernel), 0 off, 1 on.
+ *   launch  the wave kernel's launch shape (NULL: defaults).
+ * Results never depend on these values. Errors: IMIN_EINVAL for NULL g, enable outside
+ * [-1, 1], or negative launch values.
+ */
+IMIN_API int imin_set_small(imin_graph *g, int32_t enable, const imin_launch *launch);
 
 /*
  * One problem of a batched greedy call (imin_greedy_batch); the fields mean what the
@@ -184,18 +199,15 @@ typedef struct {
  * wave-per-sample launch over all their samples (samples that outgrow it go to the
  * workgroup kernel of their own graph), then one argmax per instance. Instance i's result
  * is bit-identical to imin_greedy(inst[i].g, S, nS, b, theta, seed, IMIN_AG, ...).
- *   mode          IMIN_AG only (IMIN_EINVAL otherwise).
- *   count         >= 1; the total of theta over the batch must not exceed 2^31 (IMIN_ERANGE).
- *   waves_per_cu  resident waves per compute unit of the wave kernel (0: default 20).
- *   quad_limit    frontier-chunk quad limit of the wave kernel, as for imin_set_small
- *                 (0: default 2048).
- * The launch values change speed only, never results; the graphs' own imin_set_small
- * settings do not apply here.
+ *   mode    IMIN_AG only (IMIN_EINVAL otherwise).
+ *   count   >= 1; the total of theta over the batch must not exceed 2^31 (IMIN_ERANGE).
+ *   launch  the wave kernel's launch shape (NULL: defaults); the graphs' own imin_set_small
+ *           settings do not apply here.
  * Errors: IMIN_EINVAL (any instance invalid as for imin_greedy, a graph repeated, NULL
  * inst, negative launch values), IMIN_ERANGE, IMIN_ENOMEM, IMIN_EDEVICE.
  */
 IMIN_API int imin_greedy_batch(imin_instance *inst, int32_t count, int mode,
-                               int32_t waves_per_cu, int32_t quad_limit);
+                               const imin_launch *launch);
 
 /* Human-readable text of a status code (static storage). */
 IMIN_API const char *imin_strerror(int status);

@@ -36,6 +36,20 @@ class imin_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class imin_launch(ctypes.Structure):
+    _fields_ = [("waves_per_cu", ctypes.c_int32), ("quad_limit", ctypes.c_int32),
+                ("pick_div", ctypes.c_int32)]
+
+
+def _launch(launch):
+    """None, a dict with any of the imin_launch fields, or an imin_launch."""
+    if launch is None:
+        return None
+    if isinstance(launch, imin_launch):
+        return ctypes.byref(launch)
+    return ctypes.byref(imin_launch(**{k: int(v) for k, v in launch.items()}))
+
+
 class imin_instance(ctypes.Structure):
     _fields_ = [("g", ctypes.c_void_p), ("S", ctypes.c_void_p), ("nS", ctypes.c_int32),
                 ("b", ctypes.c_int32), ("theta", ctypes.c_uint32), ("seed", ctypes.c_uint64),
@@ -71,10 +85,10 @@ def load() -> ctypes.CDLL:
     lib.imin_greedy.restype = ctypes.c_int
     lib.imin_set_launch.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
     lib.imin_set_launch.restype = ctypes.c_int
-    lib.imin_set_small.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.imin_set_small.argtypes = [P, ctypes.c_int32, P]
     lib.imin_set_small.restype = ctypes.c_int
     lib.imin_greedy_batch.argtypes = [ctypes.POINTER(imin_instance), ctypes.c_int32,
-                                      ctypes.c_int, ctypes.c_int32, ctypes.c_int32]
+                                      ctypes.c_int, P]
     lib.imin_greedy_batch.restype = ctypes.c_int
     lib.imin_strerror.argtypes = [ctypes.c_int]
     lib.imin_strerror.restype = ctypes.c_char_p
@@ -113,10 +127,8 @@ def imin_set_launch(handle: int, slots: int = 0, extra_cap: int = 0) -> None:
         raise IminError("imin_set_launch", rc)
 
 
-def imin_set_small(handle: int, enable: int = -1, waves_per_cu: int = 0,
-                   quad_limit: int = 0) -> None:
-    rc = load().imin_set_small(ctypes.c_void_p(handle), int(enable), int(waves_per_cu),
-                               int(quad_limit))
+def imin_set_small(handle: int, enable: int = -1, launch=None) -> None:
+    rc = load().imin_set_small(ctypes.c_void_p(handle), int(enable), _launch(launch))
     if rc != IMIN_OK:
         raise IminError("imin_set_small", rc)
 
@@ -150,10 +162,10 @@ def imin_greedy(handle: int, seeds, b: int, theta: int, seed: int, mode: int):
     return out[: nb[0]].copy(), st.as_dict()
 
 
-def imin_greedy_batch(problems, mode: int = IMIN_AG, waves_per_cu: int = 0,
-                      quad_limit: int = 0):
+def imin_greedy_batch(problems, mode: int = IMIN_AG, launch=None):
     """AdvancedGreedy on many problems at once. ``problems``: sequence of
-    (handle, seeds, b, theta, seed). Returns a list of (blockers, stats dict)."""
+    (handle, seeds, b, theta, seed); ``launch``: None or a dict of imin_launch fields.
+    Returns a list of (blockers, stats dict)."""
     k = len(problems)
     arr = (imin_instance * max(k, 1))()
     keep = []
@@ -174,7 +186,7 @@ def imin_greedy_batch(problems, mode: int = IMIN_AG, waves_per_cu: int = 0,
         arr[i].blockers = _p(out)
         arr[i].n_blockers = _p(nb)
         arr[i].stats = ctypes.pointer(st)
-    rc = load().imin_greedy_batch(arr, k, int(mode), int(waves_per_cu), int(quad_limit))
+    rc = load().imin_greedy_batch(arr, k, int(mode), _launch(launch))
     if rc != IMIN_OK:
         raise IminError("imin_greedy_batch", rc)
     return [(out[: nb[0]].copy(), st.as_dict()) for out, nb, st in outs]
@@ -197,8 +209,8 @@ class Graph:
     def set_launch(self, slots: int = 0, extra_cap: int = 0) -> None:
         imin_set_launch(self.handle, slots, extra_cap)
 
-    def set_small(self, enable: int = -1, waves_per_cu: int = 0, quad_limit: int = 0) -> None:
-        imin_set_small(self.handle, enable, waves_per_cu, quad_limit)
+    def set_small(self, enable: int = -1, launch=None) -> None:
+        imin_set_small(self.handle, enable, launch)
 
     def close(self) -> None:
         if self.handle:

@@ -45,8 +45,7 @@ struct imin_graph {
     imin::InstanceDesc h_inst{};
     int small_mode = -1;                     // wave kernel: -1 automatic, 0 off, 1 on
     bool small_auto_off = false;             // automatic mode found most samples too large
-    int32_t small_waves_per_cu = 0;          // 0: default
-    int32_t quad_limit = 0;                  // 0: default
+    imin_launch small_launch{0, 0, 0};       // 0 fields: defaults
     uint32_t *d_ovf = nullptr;
     uint32_t ovf_cap = 0;
     unsigned long long *d_part_d = nullptr;
@@ -72,6 +71,7 @@ constexpr uint32_t kSpillSlots = 2;
 constexpr int kStats = 6;
 constexpr int32_t kDefaultSmallWavesPerCu = 20;
 constexpr int32_t kDefaultQuadLimit = 2048;
+constexpr int32_t kDefaultPickDiv = 4;
 // In automatic mode the wave kernel is dropped for a graph once fewer than this share of
 // a round's samples finished in it.
 constexpr double kSmallKeepShare = 0.5;
@@ -234,18 +234,24 @@ bool small_enabled(const imin_graph *g)
     return !g->small_auto_off;
 }
 
-int small_grid(int num_cus, int32_t waves_per_cu)
+int small_grid(int num_cus, const imin_launch &l)
 {
-    const int32_t wpc = waves_per_cu > 0 ? waves_per_cu : kDefaultSmallWavesPerCu;
+    const int32_t wpc = l.waves_per_cu > 0 ? l.waves_per_cu : kDefaultSmallWavesPerCu;
     const int per_cu = std::max(1, (wpc + imin::kSmallWaves - 1) / imin::kSmallWaves);
     return num_cus * per_cu;
 }
 
-int small_grid(const imin_graph *g) { return small_grid(g->num_cus, g->small_waves_per_cu); }
+// The wave-kernel arguments that come from the launch shape.
+void small_shape(imin::SmallArgs &s, const imin_launch &l)
+{
+    s.quad_limit = l.quad_limit > 0 ? l.quad_limit : kDefaultQuadLimit;
+    s.pick_div = l.pick_div > 0 ? l.pick_div : kDefaultPickDiv;
+}
 
-int32_t quad_limit(int32_t q) { return q > 0 ? q : kDefaultQuadLimit; }
-
-int32_t quad_limit(const imin_graph *g) { return quad_limit(g->quad_limit); }
+bool launch_ok(const imin_launch *l)
+{
+    return !l || (l->waves_per_cu >= 0 && l->quad_limit >= 0 && l->pick_div >= 0);
+}
 
 int ensure_B(imin_graph *g, int32_t b)
 {
@@ -442,13 +448,15 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed,
         s.ninst = 1;
         s.total = theta;
         s.round = call;
-        s.quad_limit = quad_limit(g);
+        small_shape(s, g->small_launch);
         s.next = g->d_sctrl + 0;
         s.spill_inst = nullptr;
         s.spill_j = g->d_sj;
         s.spill_count = g->d_sctrl + 1;
         s.error = g->d_ctrl + 3;
-        if (!ok(imin::launch_decrease_small(s, small_grid(g), g->stream))) return IMIN_EDEVICE;
+        if (!ok(imin::launch_decrease_small(s, small_grid(g->num_cus, g->small_launch),
+                                            g->stream)))
+            return IMIN_EDEVICE;
         rc = launch_large(g, nseeds, theta, seed + call, g->d_sj, g->d_sctrl + 1);
     } else {
         rc = launch_large(g, nseeds, theta, seed + call, nullptr, nullptr);
@@ -905,21 +913,19 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
     return IMIN_OK;
 }
 
-int imin_set_small(imin_graph *g, int32_t enable, int32_t waves_per_cu, int32_t quad_limit)
+int imin_set_small(imin_graph *g, int32_t enable, const imin_launch *launch)
 {
-    if (!g || enable < -1 || enable > 1 || waves_per_cu < 0 || quad_limit < 0) return IMIN_EINVAL;
+    if (!g || enable < -1 || enable > 1 || !launch_ok(launch)) return IMIN_EINVAL;
     g->small_mode = enable;
     g->small_auto_off = false;
-    g->small_waves_per_cu = waves_per_cu;
-    g->quad_limit = quad_limit;
+    g->small_launch = launch ? *launch : imin_launch{0, 0, 0};
     return IMIN_OK;
 }
 
-int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, int32_t waves_per_cu,
-                      int32_t quad_limit_)
+int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_launch *launch)
 {
-    if (!inst || count <= 0 || mode != IMIN_AG || waves_per_cu < 0 || quad_limit_ < 0)
-        return IMIN_EINVAL;
+    if (!inst || count <= 0 || mode != IMIN_AG || !launch_ok(launch)) return IMIN_EINVAL;
+    const imin_launch shape = launch ? *launch : imin_launch{0, 0, 0};
     std::vector<BatchItem> items((size_t)count);
     std::vector<imin_graph *> graphs;
     uint64_t theta_sum = 0;
@@ -1032,13 +1038,13 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, int32_t wave
         s.ninst = active;
         s.total = prefix[(size_t)active];
         s.round = (uint32_t)r;
-        s.quad_limit = quad_limit(quad_limit_);
+        small_shape(s, shape);
         s.next = d_ctrl.p + 0;
         s.spill_inst = d_si.p;
         s.spill_j = d_sj.p;
         s.spill_count = d_ctrl.p + 1;
         s.error = d_ctrl.p + 2;
-        if (!ok(imin::launch_decrease_small(s, small_grid(g0->num_cus, waves_per_cu), bs)) ||
+        if (!ok(imin::launch_decrease_small(s, small_grid(g0->num_cus, shape), bs)) ||
             !ok(hipEventRecord(k1, bs)))
             return IMIN_EDEVICE;
         uint32_t nspill = 0;

@@ -109,6 +109,7 @@ struct SmallArgs {
     uint32_t total;           // samples of the launch: sum of the instances' theta
     uint32_t round;           // added to every instance's seed to form the key
     int32_t quad_limit;       // a frontier chunk with more edge quads goes to the large kernel
+    int32_t pick_div;         // runs of samples: about remaining / (pick_div * waves)
     uint32_t *next;           // work counter
     uint32_t *spill_inst;     // samples left to the large kernel: instance, sample index
     uint32_t *spill_j;

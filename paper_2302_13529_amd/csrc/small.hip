@@ -30,8 +30,8 @@ constexpr int kSmallBlock = kSW * 64;
 constexpr int kMaxSmallJacobiRounds = 4 * kSmallV;
 constexpr int kSeedSlots = 2;                      // cached seed quads per lane
 constexpr int kSeedCacheQuads = 64 * kSeedSlots;
-constexpr uint32_t kPickMin = 4;                   // samples per work-counter update:
-constexpr uint32_t kPickMax = 64;                  // a quarter of a fair share, within these
+constexpr uint32_t kPickMin = 4;                   // samples per work-counter update: a
+constexpr uint32_t kPickMax = 64;                  // share of what remains, within these
 
 struct WaveState {
     int gl[kSmallV];  // vertex id of each local id (local 0 is the merged seed: -1)
@@ -485,7 +485,8 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
             const uint32_t seen =
                 __hip_atomic_load(a.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (seen < a.total)
-                want = max(kPickMin, min(kPickMax, (a.total - seen) / (4u * nwaves)));
+                want = max(kPickMin,
+                           min(kPickMax, (a.total - seen) / ((uint32_t)a.pick_div * nwaves)));
             first = atomicAdd(a.next, want);
         }
         first = __builtin_amdgcn_readfirstlane(__shfl(first, 0, 64));

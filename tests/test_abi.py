@@ -76,8 +76,8 @@ def test_null_handle_is_rejected():
     assert lib.imin_decrease(None, S.ctypes.data_as(ctypes.c_void_p), 1, None, 10, 0,
                              D.ctypes.data_as(ctypes.c_void_p), None) == binding.IMIN_EINVAL
     assert lib.imin_set_launch(None, 1, 1) == binding.IMIN_EINVAL
-    assert lib.imin_set_small(None, 1, 0, 0) == binding.IMIN_EINVAL
-    assert lib.imin_greedy_batch(None, 1, 0, 0, 0) == binding.IMIN_EINVAL
+    assert lib.imin_set_small(None, 1, None) == binding.IMIN_EINVAL
+    assert lib.imin_greedy_batch(None, 1, 0, None) == binding.IMIN_EINVAL
     lib.imin_graph_destroy(None)
 
 
@@ -90,6 +90,7 @@ def test_batch_rejects_null_graph_before_touching_a_device():
     arr[0].nS = 1
     arr[0].b = 1
     arr[0].theta = 10
-    assert lib.imin_greedy_batch(arr, 1, 0, 0, 0) == binding.IMIN_EINVAL
-    assert lib.imin_greedy_batch(arr, 0, 0, 0, 0) == binding.IMIN_EINVAL
-    assert lib.imin_greedy_batch(arr, 1, 0, -1, 0) == binding.IMIN_EINVAL
+    assert lib.imin_greedy_batch(arr, 1, 0, None) == binding.IMIN_EINVAL
+    assert lib.imin_greedy_batch(arr, 0, 0, None) == binding.IMIN_EINVAL
+    bad = binding.imin_launch(-1, 0, 0)
+    assert lib.imin_greedy_batch(arr, 1, 0, ctypes.byref(bad)) == binding.IMIN_EINVAL

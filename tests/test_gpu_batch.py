@@ -106,9 +106,10 @@ def test_batch_equals_plain_and_oracle(gpu, batch16):
         assert st["live_edges"] == so["live_edges"], i
         Bp, sp = g.greedy(t.seeds, b, th, t.seed, gpu.IMIN_AG)
         assert list(Bp) == list(B), i
-    for wpc, ql in ((4, 0), (8, 1), (32, 64)):
-        case(f"batched AG, waves_per_cu={wpc} quad_limit={ql}")
-        res2 = gpu.imin_greedy_batch(probs, gpu.IMIN_AG, wpc, ql)
+    for wpc, ql, pd in ((4, 0, 0), (8, 1, 1), (32, 64, 16)):
+        case(f"batched AG, waves_per_cu={wpc} quad_limit={ql} pick_div={pd}")
+        res2 = gpu.imin_greedy_batch(probs, gpu.IMIN_AG,
+                                     dict(waves_per_cu=wpc, quad_limit=ql, pick_div=pd))
         for (B, st), (B2, st2) in zip(res, res2):
             assert list(B) == list(B2)
             assert st["reached"] == st2["reached"] and st["live_edges"] == st2["live_edges"]
@@ -176,3 +177,22 @@ def test_batch_errors_leave_outputs_untouched(gpu):
     assert list(res[0][0]) == [1, 2] and list(res[1][0]) == [4, 0]
     g.close()
     h.close()
+
+
+def test_autotuned_launch_gives_identical_results(gpu, batch16, tmp_path, monkeypatch):
+    from paper_2302_13529_amd import autotune
+    monkeypatch.setenv("IMIN_TUNE_CACHE", str(tmp_path / "tuned.json"))
+    insts = batch16[:8]
+    graphs = [gpu.Graph(t.row_ptr, t.col, t.prob) for t in insts]
+    probs = [(g.handle, t.seeds, 3, 200, t.seed) for g, t in zip(graphs, insts)]
+    case("autotune a batch of 8 on a reduced grid")
+    grid = {"waves_per_cu": [8, 16], "quad_limit": [256, 2048], "pick_div": [2, 4]}
+    best, ms, table = autotune.tune_batch(probs, grid=grid, repeats=1)
+    assert set(best) == set(grid) and ms > 0 and len(table) >= 3
+    ref = gpu.imin_greedy_batch(probs)
+    res = gpu.imin_greedy_batch(probs, gpu.IMIN_AG, best)
+    assert [list(b) for b, _ in ref] == [list(b) for b, _ in res]
+    key, launch = autotune.tuned_batch_launch(insts, probs, tune_if_missing=False)
+    assert launch is None or isinstance(launch, dict)
+    for g in graphs:
+        g.close()

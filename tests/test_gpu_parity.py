@@ -79,7 +79,7 @@ def test_launch_shapes_and_spill_give_identical_counts(gpu, tiny):
     g.set_launch(0, 0)
     for waves, ql in ((1, 0), (4, 1), (8, 3), (20, 0), (32, 100000)):
         case(f"wave kernel waves_per_cu={waves} quad_limit={ql}")
-        g.set_small(1, waves, ql)
+        g.set_small(1, dict(waves_per_cu=waves, quad_limit=ql))
         D, s = g.decrease(t.seeds, None, 700, 9)
         assert np.array_equal(D, D0)
         assert s["reached"] == s0["reached"] and s["live_edges"] == s0["live_edges"]
@@ -140,7 +140,7 @@ def test_edge_cases(gpu, item):
         check_decrease(g, n, row_ptr, col, prob, seeds, blocked, theta, key, label)
     # wave kernel off, and on with every frontier chunk handed over at once
     for enable, ql in ((0, 0), (1, 1), (1, 0)):
-        g.set_small(enable, 0, ql)
+        g.set_small(enable, dict(quad_limit=ql))
         check_decrease(g, n, row_ptr, col, prob, seeds, blocked, 97, 3,
                        f"{label}/small={enable},{ql}")
     g.set_small(0)
