@@ -114,6 +114,18 @@ IMIN_API int imin_decrease(imin_graph *g, const int32_t *S, int32_t nS, const ui
                   uint32_t theta, uint64_t seed, uint64_t *counts, imin_stats *stats);
 
 /*
+ * imin_spread -- Monte-Carlo estimate of the expected spread E(S, G[V \ B]) (Definition 1,
+ * seeds counted) from theta live-edge samples: by Lemma 1 the number of vertices a sample
+ * reaches from S is an unbiased estimate. The samples are those of imin_decrease with the
+ * same arguments (same coins), with the dominator work left out.
+ *   spread   receives |S| + (sum over samples of reached non-seed vertices) / theta, where
+ *            |S| counts distinct seeds; stats->reached holds that exact sum.
+ * Other arguments and errors as for imin_decrease (counts replaced by spread).
+ */
+IMIN_API int imin_spread(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *blocked,
+                         uint32_t theta, uint64_t seed, double *spread, imin_stats *stats);
+
+/*
  * imin_greedy -- AdvancedGreedy (Algorithm 3) or GreedyReplace (Algorithm 4).
  *   b          budget, b >= 0.
  *   theta      samples per Algorithm 2 call, 1 <= theta <= 2^31 (IMIN_ERANGE above).

@@ -1,10 +1,10 @@
 """ctypes binding of libimin (include/imin.h): argument marshalling only.
 
-The functions keep the C names (``imin_graph_create``, ``imin_decrease``, ``imin_greedy``,
-``imin_greedy_batch``, ``imin_set_launch``, ``imin_set_small``, ``imin_graph_destroy``,
-``imin_strerror``); ``Graph`` wraps them for convenience. Every step of the estimate runs in
-the library's HIP kernels; if the library is missing this module raises instead of
-computing anything itself.
+The functions keep the C names (``imin_graph_create``, ``imin_decrease``, ``imin_spread``,
+``imin_greedy``, ``imin_greedy_batch``, ``imin_set_launch``, ``imin_set_small``,
+``imin_graph_destroy``, ``imin_strerror``); ``Graph`` wraps them for convenience. Every step
+of the estimate runs in the library's HIP kernels; if the library is missing this module
+raises instead of computing anything itself.
 """
 from __future__ import annotations
 
@@ -80,6 +80,9 @@ def load() -> ctypes.CDLL:
     lib.imin_decrease.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_uint32, ctypes.c_uint64, P,
                                   ctypes.POINTER(imin_stats)]
     lib.imin_decrease.restype = ctypes.c_int
+    lib.imin_spread.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_uint32, ctypes.c_uint64,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(imin_stats)]
+    lib.imin_spread.restype = ctypes.c_int
     lib.imin_greedy.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                 ctypes.c_uint64, ctypes.c_int, P, P, ctypes.POINTER(imin_stats)]
     lib.imin_greedy.restype = ctypes.c_int
@@ -148,6 +151,21 @@ def imin_decrease(handle: int, n: int, seeds, blocked, theta: int, seed: int):
     return D, st.as_dict()
 
 
+def imin_spread(handle: int, n: int, seeds, blocked, theta: int, seed: int):
+    """Expected-spread estimate |S| + reached/theta and the stats dict."""
+    S = np.ascontiguousarray(seeds, dtype=np.int32)
+    blk = None if blocked is None else np.ascontiguousarray(blocked, dtype=np.uint8)
+    if blk is not None and blk.shape[0] != n:
+        raise ValueError("blocked must have n entries")
+    out = ctypes.c_double()
+    st = imin_stats()
+    rc = load().imin_spread(ctypes.c_void_p(handle), _p(S), S.shape[0], _p(blk), int(theta),
+                            int(seed) & (2**64 - 1), ctypes.byref(out), ctypes.byref(st))
+    if rc != IMIN_OK:
+        raise IminError("imin_spread", rc)
+    return out.value, st.as_dict()
+
+
 def imin_greedy(handle: int, seeds, b: int, theta: int, seed: int, mode: int):
     """Blocker slots (int32) and the summed stats of AG (mode 0) or GR (mode 1)."""
     S = np.ascontiguousarray(seeds, dtype=np.int32)
@@ -202,6 +220,9 @@ class Graph:
 
     def decrease(self, seeds, blocked=None, theta: int = 1000, seed: int = 0):
         return imin_decrease(self.handle, self.n, seeds, blocked, theta, seed)
+
+    def spread(self, seeds, blocked=None, theta: int = 100000, seed: int = 0):
+        return imin_spread(self.handle, self.n, seeds, blocked, theta, seed)
 
     def greedy(self, seeds, b: int, theta: int, seed: int = 0, mode: int = IMIN_AG):
         return imin_greedy(self.handle, seeds, b, theta, seed, mode)

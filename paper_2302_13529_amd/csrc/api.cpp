@@ -384,7 +384,7 @@ int kernel_events(imin_graph *g, hipEvent_t *a, hipEvent_t *b)
 // the device list `list` of *count samples (at most theta), then the large-scratch launch
 // for the samples that overflowed it. D and the stats accumulate.
 int launch_large(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key,
-                 const uint32_t *list, const uint32_t *count)
+                 const uint32_t *list, const uint32_t *count, bool reach_only = false)
 {
     int rc = guard_epochs(g, g->main_ws, theta);
     if (rc) return rc;
@@ -414,6 +414,7 @@ int launch_large(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key,
     a.ovf_count = g->d_ctrl + 2;
     a.error = g->d_ctrl + 3;
     a.spill_ok = spill ? 1 : 0;
+    a.reach_only = reach_only ? 1 : 0;
     a.ws = g->main_ws;
     a.ws.slots = (int32_t)std::min<uint32_t>((uint32_t)g->main_ws.slots, theta);
     if (!ok(imin::launch_decrease(a, g->stream))) return IMIN_EDEVICE;
@@ -431,10 +432,11 @@ int launch_large(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key,
 // One call of Algorithm 2 with Philox key seed + call, leaving D on the device. With the
 // wave kernel on, it runs every sample first and leaves the ones that outgrow it to the
 // workgroup kernel, through a device-side list (no host round trip).
-int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed, uint32_t call)
+int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed, uint32_t call,
+                   bool reach_only = false)
 {
     const bool small = small_enabled(g);
-    if (!ok(imin::launch_fill_u64(g->d_D, g->n, 0, g->stream)) ||
+    if ((!reach_only && !ok(imin::launch_fill_u64(g->d_D, g->n, 0, g->stream))) ||
         (small && !ok(imin::launch_fill_u32(g->d_sctrl, 2, 0, g->stream))))
         return IMIN_EDEVICE;
     hipEvent_t k0, k1;
@@ -449,6 +451,7 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed,
         s.total = theta;
         s.round = call;
         small_shape(s, g->small_launch);
+        s.reach_only = reach_only ? 1 : 0;
         s.next = g->d_sctrl + 0;
         s.spill_inst = nullptr;
         s.spill_j = g->d_sj;
@@ -457,9 +460,9 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed,
         if (!ok(imin::launch_decrease_small(s, small_grid(g->num_cus, g->small_launch),
                                             g->stream)))
             return IMIN_EDEVICE;
-        rc = launch_large(g, nseeds, theta, seed + call, g->d_sj, g->d_sctrl + 1);
+        rc = launch_large(g, nseeds, theta, seed + call, g->d_sj, g->d_sctrl + 1, reach_only);
     } else {
-        rc = launch_large(g, nseeds, theta, seed + call, nullptr, nullptr);
+        rc = launch_large(g, nseeds, theta, seed + call, nullptr, nullptr, reach_only);
     }
     if (rc) return rc;
     if (!ok(hipEventRecord(k1, g->stream))) return IMIN_EDEVICE;
@@ -733,11 +736,18 @@ int imin_set_launch(imin_graph *g, int32_t slots, int64_t extra_cap)
     return IMIN_OK;
 }
 
-int imin_decrease(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *blocked,
-                  uint32_t theta, uint64_t seed, uint64_t *counts, imin_stats *stats)
+}  // extern "C"
+
+namespace {
+
+// One Algorithm 2 call (counts != NULL) or a reachability-only estimate (counts == NULL).
+int one_call(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *blocked,
+             uint32_t theta, uint64_t seed, uint64_t *counts, imin_stats *stats,
+             int32_t *n_seeds)
 {
-    if (!g || !counts || theta == 0) return IMIN_EINVAL;
+    if (!g || theta == 0) return IMIN_EINVAL;
     if (theta > kMaxTheta) return IMIN_ERANGE;
+    const bool reach_only = counts == nullptr;
     std::vector<int32_t> seeds;
     std::vector<uint32_t> inelig;
     int rc = seed_setup(g, S, nS, seeds, inelig);
@@ -761,12 +771,15 @@ int imin_decrease(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *bl
     rc = upload_call_state(g, seeds, inelig, seed, theta);
     if (rc) return rc;
     const bool small = small_enabled(g);
-    rc = decrease_round(g, (int32_t)seeds.size(), theta, seed, 0);
+    rc = decrease_round(g, (int32_t)seeds.size(), theta, seed, 0, reach_only);
     if (rc) return rc;
-    std::vector<unsigned long long> D((size_t)g->n);
-    if (!ok(hipMemcpyAsync(D.data(), g->d_D, (size_t)g->n * sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, g->stream)))
-        return IMIN_EDEVICE;
+    std::vector<unsigned long long> D;
+    if (!reach_only) {
+        D.resize((size_t)g->n);
+        if (!ok(hipMemcpyAsync(D.data(), g->d_D, (size_t)g->n * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, g->stream)))
+            return IMIN_EDEVICE;
+    }
     imin_stats st;
     rc = finish_call(g, &st);
     if (rc) return rc;
@@ -774,7 +787,33 @@ int imin_decrease(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *bl
     if (small && g->small_mode == -1 &&
         (double)st.wave_samples < kSmallKeepShare * (double)st.samples)
         g->small_auto_off = true;
-    std::memcpy(counts, D.data(), (size_t)g->n * sizeof(uint64_t));
+    if (!reach_only) std::memcpy(counts, D.data(), (size_t)g->n * sizeof(uint64_t));
+    if (stats) *stats = st;
+    *n_seeds = (int32_t)seeds.size();
+    return IMIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int imin_decrease(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *blocked,
+                  uint32_t theta, uint64_t seed, uint64_t *counts, imin_stats *stats)
+{
+    if (!counts) return IMIN_EINVAL;
+    int32_t ns = 0;
+    return one_call(g, S, nS, blocked, theta, seed, counts, stats, &ns);
+}
+
+int imin_spread(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *blocked,
+                uint32_t theta, uint64_t seed, double *spread, imin_stats *stats)
+{
+    if (!spread) return IMIN_EINVAL;
+    imin_stats st;
+    int32_t ns = 0;
+    const int rc = one_call(g, S, nS, blocked, theta, seed, nullptr, &st, &ns);
+    if (rc) return rc;
+    *spread = (double)ns + (double)st.reached / (double)theta;
     if (stats) *stats = st;
     return IMIN_OK;
 }

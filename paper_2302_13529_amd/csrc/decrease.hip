@@ -102,7 +102,7 @@ __device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv,
         } else {
             sh.ovf = 1;
         }
-    } else if (src != 0) {
+    } else if (src != 0 && !a.reach_only) {
         const int x = atomicAdd(&sh.nextra, 1);
         if (x < a.ws.xcap) sv.extra[x] = make_int2(src, w);
         else sh.ovf = 1;
@@ -278,6 +278,7 @@ void decrease_kernel(DecreaseArgs a)
         wave_add(&sh.live, p_live);
         const int nV = sh.tail;
         const int nX = sh.nextra;
+        if (a.reach_only) L = 1;  // reachability alone: no dominators, no counts
 
         // Extra edges: resolve the target vertex to its local id.
         for (int x = tid; x < nX; x += kBlock) {

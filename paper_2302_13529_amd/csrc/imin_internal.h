@@ -66,6 +66,7 @@ struct DecreaseArgs {
     uint32_t *ovf_count;
     uint32_t *error;         // set when a sample overflows with spill_ok == 0
     int32_t spill_ok;
+    int32_t reach_only;      // count reached vertices only (spread estimates)
     Workspace ws;
 };
 
@@ -110,6 +111,7 @@ struct SmallArgs {
     uint32_t round;           // added to every instance's seed to form the key
     int32_t quad_limit;       // a frontier chunk with more edge quads goes to the large kernel
     int32_t pick_div;         // runs of samples: about remaining / (pick_div * waves)
+    int32_t reach_only;       // count reached vertices only (spread estimates)
     uint32_t *next;           // work counter
     uint32_t *spill_inst;     // samples left to the large kernel: instance, sample index
     uint32_t *spill_j;

@@ -115,6 +115,7 @@ __device__ __forceinline__ int mirror_find(const Mirror &m, int c)
 struct SampleCtx {
     int nV, nX, L;     // uniform
     int ovf;           // uniform
+    int reach_only;    // uniform: keep no extra edges
     uint32_t live;     // per lane, summed at the end
     uint32_t scanned;  // per lane, summed at the end
 };
@@ -135,7 +136,7 @@ __device__ __forceinline__ void claim(WaveState &ws, Mirror &m, SampleCtx &cx, i
             ws.pa[id] = src;
             ws.td[id] = src;
         }
-    } else if (src != 0) {
+    } else if (src != 0 && !cx.reach_only) {
         if (cx.nX >= kSmallX) {
             cx.ovf = 1;
             return;
@@ -380,6 +381,7 @@ __device__ bool run_sample(const SmallArgs &a, const InstanceDesc &I, const Seed
     cx.nX = 0;
     cx.L = 1;
     cx.ovf = 0;
+    cx.reach_only = a.reach_only;
     cx.live = 0;
     cx.scanned = 0;
     wave_sync();
@@ -405,7 +407,7 @@ __device__ bool run_sample(const SmallArgs &a, const InstanceDesc &I, const Seed
         ++cx.L;
     }
     if (cx.ovf) return false;
-    const int nV = cx.nV, nX = cx.nX, L = cx.L;
+    const int nV = cx.nV, nX = cx.nX, L = a.reach_only ? 1 : cx.L;
     wave_sync();
 
     // Dominator tree: Jacobi NCA steps over the extra edges (as in the workgroup kernel).

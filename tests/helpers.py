@@ -139,3 +139,27 @@ def within_sigmas(est, mean, second, theta, k=4.0, floor=1e-12):
     var = max(second - mean * mean, 0.0)
     se = math.sqrt(var / theta)
     return abs(est - mean) <= k * se + floor
+
+
+def spread_moments(n, row_ptr, col, prob, seeds, blocked=None):
+    """Exact first and second moments of the number of active vertices (seeds counted) by
+    enumerating every live-edge world (at most 20 uncertain edges)."""
+    p = effective_p(prob)
+    removed = np.zeros(n, dtype=bool) if blocked is None else np.asarray(blocked, dtype=bool)
+    unc = [e for e in range(len(col)) if 0.0 < p[e] < 1.0]
+    if len(unc) > 20:
+        raise ValueError("too many uncertain edges to enumerate")
+    base = p >= 1.0
+    E = E2 = 0.0
+    for bits in itertools.product([0, 1], repeat=len(unc)):
+        live = base.copy()
+        w = 1.0
+        for e, b in zip(unc, bits):
+            live[e] = bool(b)
+            w *= p[e] if b else 1.0 - p[e]
+        if w == 0.0:
+            continue
+        size = int(reach(n, row_ptr, col, live, seeds, removed).sum())
+        E += w * size
+        E2 += w * size * size
+    return E, E2
