@@ -1,8 +1,7 @@
 // api.cpp -- host side of libimin: validation, device residency of the graph, scratch
 // sizing, and the greedy drivers (Algorithms 3 and 4 of arXiv 2302.13529) as device-side
 // round loops. Every step of the estimate runs in the kernels of decrease.hip/select.hip.
-#include "imin.h"
-#include "imin_internal.h"
+#include "graph.h"
 
 #include <algorithm>
 #include <array>
@@ -14,61 +13,12 @@
 using imin::DecreaseArgs;
 using imin::Workspace;
 
-struct imin_graph {
-    int device = 0;
-    int32_t n = 0;
-    int32_t m = 0;
-    int num_cus = 1;
-    std::vector<int32_t> row_ptr;  // host copies: out-neighbours of the seeds (GR)
-    std::vector<int32_t> col;
-    int32_t *d_row_ptr = nullptr;
-    uint4 *d_col4 = nullptr;      // edge targets, 4 per quad, padded to a whole quad
-    uint4 *d_thr4 = nullptr;      // working live thresholds, same layout: 0 on every edge into
-                                  // a vertex of `masked`
-    uint4 *d_thr_orig = nullptr;  // the thresholds ceil(p * 2^24) as created
-    int32_t *d_in_ptr = nullptr;  // in-edges of v: d_in_edge[d_in_ptr[v] .. d_in_ptr[v+1])
-    int32_t *d_in_edge = nullptr; // edge ids, grouped by target
-    hipStream_t stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    int32_t words = 0;                       // 32-bit words of a vertex bitmap
-    uint32_t *d_inelig = nullptr;            // seeds and blocked vertices
-    uint32_t *d_cand = nullptr;              // GR candidate set CB
-    int32_t *d_seeds = nullptr;              // distinct seeds (capacity n)
-    unsigned long long *d_D = nullptr;       // n
-    unsigned long long *d_stats = nullptr;   // kStats: samples, reached, scanned, live,
-                                             // spilled, wave-kernel samples
-    uint32_t *d_ctrl = nullptr;              // 4: next main, next spill, spill count, error
-    uint32_t *d_sctrl = nullptr;             // 2: wave-kernel work counter, samples it left
-    uint32_t *d_sj = nullptr;                // samples the wave kernel left to the large one
-    uint32_t sj_cap = 0;
-    imin::InstanceDesc *d_inst = nullptr;    // this graph as the one instance of a wave launch
-    imin::InstanceDesc h_inst{};
-    int small_mode = -1;                     // wave kernel: -1 automatic, 0 off, 1 on
-    bool small_auto_off = false;             // automatic mode found most samples too large
-    imin_launch small_launch{0, 0, 0};       // 0 fields: defaults
-    uint32_t *d_ovf = nullptr;
-    uint32_t ovf_cap = 0;
-    unsigned long long *d_part_d = nullptr;
-    int32_t *d_part_i = nullptr;
-    int32_t parts = 4096;
-    int32_t *d_B = nullptr;
-    int32_t B_cap = 0;
-    int32_t *d_x = nullptr;
-    Workspace main_ws, big_ws;
-    std::vector<int32_t> masked;       // vertices whose in-edges have threshold 0 in d_thr4
-    std::vector<int32_t> mask_prev;    // the previous call's list, kept while copies run
-    bool mask_known = true;            // false while a call runs, and after one that failed
-    int32_t *d_list = nullptr;         // 2n: device copies of the two lists above
-    std::vector<hipEvent_t> kev;  // pairs around each decrease launch of the current call
-    size_t kev_used = 0;
-    int32_t force_slots = 0;
-    int64_t force_xcap = 0;
-};
 
-namespace {
+
+namespace imin {
+namespace host {
 
 constexpr uint32_t kSpillSlots = 2;
-constexpr int kStats = 6;
 constexpr int32_t kDefaultSmallWavesPerCu = 20;
 constexpr int32_t kDefaultQuadLimit = 2048;
 constexpr int32_t kDefaultPickDiv = 4;
@@ -77,10 +27,7 @@ constexpr int32_t kDefaultPickDiv = 4;
 constexpr double kSmallKeepShare = 0.5;
 // Workgroup-kernel slots while the wave kernel takes the samples first (it leaves few).
 constexpr int32_t kSmallModeSlots = 64;
-// The per-launch work counter is 32-bit and every workgroup takes one index past the end.
-constexpr uint32_t kMaxTheta = 1u << 31;
 
-bool ok(hipError_t e) { return e == hipSuccess; }
 
 // ceil(p * 2^24) for p in [0, 1]; the product by a power of two is exact in fp32.
 uint32_t live_threshold(float p)
@@ -90,12 +37,6 @@ uint32_t live_threshold(float p)
     return (uint32_t)std::ceil(p * 16777216.0f);
 }
 
-template <class T>
-void dfree(T *&p)
-{
-    if (p) (void)hipFree(p);
-    p = nullptr;
-}
 
 void free_ws(Workspace &ws)
 {
@@ -113,12 +54,13 @@ size_t slot_bytes(int64_t n, int64_t lcap, int64_t xcap)
            (size_t)(lcap + 1) * sizeof(int32_t) + (size_t)xcap * sizeof(int2) + sizeof(uint32_t);
 }
 
-int alloc_ws(imin_graph *g, Workspace &ws, int32_t slots, int64_t lcap, int64_t xcap)
+int alloc_ws(Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap,
+             hipStream_t stream)
 {
-    if (ws.slots == slots && ws.lcap == lcap && ws.xcap == xcap) return IMIN_OK;
+    if (ws.slots == slots && ws.n == n && ws.lcap == lcap && ws.xcap == xcap) return IMIN_OK;
     free_ws(ws);
     const size_t S = (size_t)slots;
-    bool good = ok(hipMalloc(&ws.map, S * (size_t)g->n * sizeof(imin::SlotEntry))) &&
+    bool good = ok(hipMalloc(&ws.map, S * (size_t)n * sizeof(imin::SlotEntry))) &&
                 ok(hipMalloc(&ws.loc, S * (size_t)lcap * sizeof(imin::LocalVtx))) &&
                 ok(hipMalloc(&ws.lvl, S * (size_t)(lcap + 1) * sizeof(int32_t))) &&
                 ok(hipMalloc(&ws.extra, S * (size_t)std::max<int64_t>(xcap, 1) * sizeof(int2))) &&
@@ -128,16 +70,17 @@ int alloc_ws(imin_graph *g, Workspace &ws, int32_t slots, int64_t lcap, int64_t 
         (void)hipGetLastError();
         return IMIN_ENOMEM;
     }
-    if (!ok(hipMemsetAsync(ws.map, 0, S * (size_t)g->n * sizeof(imin::SlotEntry), g->stream)) ||
-        !ok(hipMemsetAsync(ws.epoch, 0, S * sizeof(uint32_t), g->stream))) {
+    if (!ok(hipMemsetAsync(ws.map, 0, S * (size_t)n * sizeof(imin::SlotEntry), stream)) ||
+        !ok(hipMemsetAsync(ws.epoch, 0, S * sizeof(uint32_t), stream))) {
         free_ws(ws);
         return IMIN_EDEVICE;
     }
     ws.slots = slots;
+    ws.n = n;
     ws.lcap = lcap;
     ws.xcap = xcap;
     ws.epochs_used = 0;
-    ws.bytes = S * slot_bytes(g->n, lcap, xcap);
+    ws.bytes = S * slot_bytes(n, lcap, xcap);
     return IMIN_OK;
 }
 
@@ -170,10 +113,10 @@ int size_workspaces(imin_graph *g, int32_t max_slots)
             (have >= slots || (max_slots == 0 && have > kSmallModeSlots)))
             slots = have;
     }
-    int rc = alloc_ws(g, g->main_ws, slots, lcap, xcap);
+    int rc = alloc_ws(g->main_ws, g->n, slots, lcap, xcap, g->stream);
     if (rc) return rc;
     if (xcap < xmax) {
-        rc = alloc_ws(g, g->big_ws, kSpillSlots, lcap, xmax);
+        rc = alloc_ws(g->big_ws, g->n, kSpillSlots, lcap, xmax, g->stream);
         if (rc) return rc;
     } else {
         free_ws(g->big_ws);
@@ -188,16 +131,16 @@ int prepare_workspaces(imin_graph *g)
 
 // Keep every slot's 32-bit epoch from wrapping: a launch of theta samples raises any slot's
 // epoch by at most theta.
-int guard_epochs(imin_graph *g, Workspace &ws, uint32_t theta)
+int guard_epochs(Workspace &ws, uint32_t theta, hipStream_t stream)
 {
     if (ws.slots == 0) return IMIN_OK;
     if (ws.epochs_used + theta + 1 < 0xFFFFFFFFull) {
         ws.epochs_used += theta;
         return IMIN_OK;
     }
-    if (!ok(hipMemsetAsync(ws.map, 0, (size_t)ws.slots * g->n * sizeof(imin::SlotEntry),
-                           g->stream)) ||
-        !ok(hipMemsetAsync(ws.epoch, 0, (size_t)ws.slots * sizeof(uint32_t), g->stream)))
+    if (!ok(hipMemsetAsync(ws.map, 0, (size_t)ws.slots * ws.n * sizeof(imin::SlotEntry),
+                           stream)) ||
+        !ok(hipMemsetAsync(ws.epoch, 0, (size_t)ws.slots * sizeof(uint32_t), stream)))
         return IMIN_EDEVICE;
     ws.epochs_used = theta;
     return IMIN_OK;
@@ -383,50 +326,184 @@ int kernel_events(imin_graph *g, hipEvent_t *a, hipEvent_t *b)
 // The workgroup-per-sample kernel with Philox key `key` over samples 0..theta-1, or over
 // the device list `list` of *count samples (at most theta), then the large-scratch launch
 // for the samples that overflowed it. D and the stats accumulate.
-int launch_large(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key,
-                 const uint32_t *list, const uint32_t *count, bool reach_only = false)
+int launch_large_on(imin_graph *g, const LargeTarget &t, uint32_t theta, uint64_t key,
+                    const uint32_t *list, const uint32_t *count, bool reach_only)
 {
-    int rc = guard_epochs(g, g->main_ws, theta);
+    int rc = guard_epochs(*t.main_ws, theta, g->stream);
     if (rc) return rc;
-    const bool spill = g->big_ws.slots > 0;
+    const bool spill = t.big_ws->slots > 0;
     if (spill) {
-        rc = guard_epochs(g, g->big_ws, theta);
+        rc = guard_epochs(*t.big_ws, theta, g->stream);
         if (rc) return rc;
     }
-    if (!ok(imin::launch_fill_u32(g->d_ctrl, 3, 0, g->stream))) return IMIN_EDEVICE;
+    if (!ok(imin::launch_fill_u32(t.ctrl, 3, 0, g->stream))) return IMIN_EDEVICE;
     DecreaseArgs a;
     std::memset(&a, 0, sizeof(a));
     a.row_ptr = g->d_row_ptr;
     a.col4 = g->d_col4;
-    a.thr4 = g->d_thr4;
-    a.seeds = g->d_seeds;
-    a.nseeds = nseeds;
+    a.thr4 = t.thr4;
+    a.seeds = t.seeds;
+    a.nseeds = t.nseeds;
     a.n = g->n;
     a.key_lo = (uint32_t)key;
     a.key_hi = (uint32_t)(key >> 32);
     a.theta = theta;
     a.sample_list = list;
     a.sample_count = count;
-    a.next = g->d_ctrl + 0;
-    a.D = g->d_D;
-    a.stats = g->d_stats;
-    a.ovf_list = g->d_ovf;
-    a.ovf_count = g->d_ctrl + 2;
-    a.error = g->d_ctrl + 3;
+    a.next = t.ctrl + 0;
+    a.D = t.D;
+    a.stats = t.stats;
+    a.ovf_list = t.ovf;
+    a.ovf_count = t.ctrl + 2;
+    a.error = t.ctrl + 3;
     a.spill_ok = spill ? 1 : 0;
     a.reach_only = reach_only ? 1 : 0;
-    a.ws = g->main_ws;
-    a.ws.slots = (int32_t)std::min<uint32_t>((uint32_t)g->main_ws.slots, theta);
+    a.ws = *t.main_ws;
+    a.ws.slots = (int32_t)std::min<uint32_t>((uint32_t)t.main_ws->slots, theta);
     if (!ok(imin::launch_decrease(a, g->stream))) return IMIN_EDEVICE;
     if (spill) {
-        a.sample_list = g->d_ovf;
-        a.sample_count = g->d_ctrl + 2;
-        a.next = g->d_ctrl + 1;
+        a.sample_list = t.ovf;
+        a.sample_count = t.ctrl + 2;
+        a.next = t.ctrl + 1;
         a.spill_ok = 0;
-        a.ws = g->big_ws;
+        a.ws = *t.big_ws;
         if (!ok(imin::launch_decrease(a, g->stream))) return IMIN_EDEVICE;
     }
     return IMIN_OK;
+}
+
+void multi_free(MultiScratch &ms)
+{
+    free_ws(ms.main_ws);
+    free_ws(ms.big_ws);
+    dfree(ms.ctrl);
+    dfree(ms.si);
+    dfree(ms.sj);
+    dfree(ms.oi);
+    dfree(ms.oj);
+    ms.n = ms.m = 0;
+    ms.cap = 0;
+}
+
+int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uint32_t cap,
+                hipStream_t stream)
+{
+    const int64_t lcap = max_n + 1;
+    const int64_t xmax = max_m + 1;
+    const int64_t xcap = std::min<int64_t>(std::max<int64_t>(4096, lcap / 4), xmax);
+    // one workgroup slot per compute unit: samples that outgrow the wave kernel are few
+    int rc = alloc_ws(ms.main_ws, max_n, std::max(1, num_cus), lcap, xcap, stream);
+    if (rc) return rc;
+    if (xcap < xmax) {
+        rc = alloc_ws(ms.big_ws, max_n, (int32_t)kSpillSlots, lcap, xmax, stream);
+        if (rc) return rc;
+    } else {
+        free_ws(ms.big_ws);
+    }
+    if (cap > ms.cap) {
+        dfree(ms.si);
+        dfree(ms.sj);
+        dfree(ms.oi);
+        dfree(ms.oj);
+        ms.cap = 0;
+        if (!ok(hipMalloc(&ms.si, (size_t)cap * sizeof(uint32_t))) ||
+            !ok(hipMalloc(&ms.sj, (size_t)cap * sizeof(uint32_t))) ||
+            !ok(hipMalloc(&ms.oi, (size_t)cap * sizeof(uint32_t))) ||
+            !ok(hipMalloc(&ms.oj, (size_t)cap * sizeof(uint32_t)))) {
+            (void)hipGetLastError();
+            return IMIN_ENOMEM;
+        }
+        ms.cap = cap;
+    }
+    if (!ms.ctrl && !ok(hipMalloc(&ms.ctrl, 7 * sizeof(uint32_t)))) {
+        (void)hipGetLastError();
+        return IMIN_ENOMEM;
+    }
+    if (!ok(imin::launch_fill_u32(ms.ctrl, 7, 0, stream))) return IMIN_EDEVICE;
+    ms.n = max_n;
+    ms.m = max_m;
+    return IMIN_OK;
+}
+
+int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst, uint32_t total,
+                uint32_t round, const imin_launch &shape, int num_cus, bool select,
+                int32_t slot, hipStream_t stream)
+{
+    if (total > ms.cap) return IMIN_ERANGE;
+    int rc = guard_epochs(ms.main_ws, total, stream);
+    if (rc) return rc;
+    const bool spill = ms.big_ws.slots > 0;
+    if (spill) {
+        rc = guard_epochs(ms.big_ws, total, stream);
+        if (rc) return rc;
+    }
+    // words 0, 1, 3, 4, 5 restart every round; the error words 2 and 6 accumulate
+    if (!ok(imin::launch_batch_zero(inst, ninst, stream)) ||
+        !ok(imin::launch_fill_u32(ms.ctrl, 2, 0, stream)) ||
+        !ok(imin::launch_fill_u32(ms.ctrl + 3, 3, 0, stream)))
+        return IMIN_EDEVICE;
+    imin::SmallArgs s;
+    std::memset(&s, 0, sizeof(s));
+    s.inst = inst;
+    s.ninst = ninst;
+    s.total = total;
+    s.round = round;
+    small_shape(s, shape);
+    s.next = ms.ctrl + 0;
+    s.spill_inst = ms.si;
+    s.spill_j = ms.sj;
+    s.spill_count = ms.ctrl + 1;
+    s.error = ms.ctrl + 2;
+    if (!ok(imin::launch_decrease_small(s, small_grid(num_cus, shape), stream)))
+        return IMIN_EDEVICE;
+    DecreaseArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = (int32_t)ms.n;
+    a.theta = total;
+    a.sample_list = ms.sj;
+    a.sample_count = ms.ctrl + 1;
+    a.next = ms.ctrl + 3;
+    a.ovf_list = ms.oj;
+    a.ovf_count = ms.ctrl + 5;
+    a.error = ms.ctrl + 6;
+    a.spill_ok = spill ? 1 : 0;
+    a.ws = ms.main_ws;
+    a.inst = inst;
+    a.sample_inst = ms.si;
+    a.ovf_inst = ms.oi;
+    a.round = round;
+    if (!ok(imin::launch_decrease(a, stream))) return IMIN_EDEVICE;
+    if (spill) {
+        a.sample_list = ms.oj;
+        a.sample_inst = ms.oi;
+        a.sample_count = ms.ctrl + 5;
+        a.next = ms.ctrl + 4;
+        a.spill_ok = 0;
+        a.ws = ms.big_ws;
+        if (!ok(imin::launch_decrease(a, stream))) return IMIN_EDEVICE;
+    }
+    if (select && !ok(imin::launch_batch_argmax(inst, ninst, slot, stream))) return IMIN_EDEVICE;
+    return IMIN_OK;
+}
+
+int multi_errors(MultiScratch &ms, uint32_t *wave_err, uint32_t *wg_err, hipStream_t stream)
+{
+    uint32_t w[7];
+    if (!ok(hipMemcpyAsync(w, ms.ctrl, sizeof(w), hipMemcpyDeviceToHost, stream)) ||
+        !ok(hipStreamSynchronize(stream)))
+        return IMIN_EDEVICE;
+    *wave_err = w[2];
+    *wg_err = w[6];
+    return IMIN_OK;
+}
+
+// The graph's own call state as the target of the workgroup kernel.
+int launch_large(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key,
+                 const uint32_t *list, const uint32_t *count, bool reach_only = false)
+{
+    LargeTarget t{g->d_thr4, g->d_seeds, nseeds, g->d_D, g->d_stats, g->d_ctrl, g->d_ovf,
+                  &g->main_ws, &g->big_ws};
+    return launch_large_on(g, t, theta, key, list, count, reach_only);
 }
 
 // One call of Algorithm 2 with Philox key seed + call, leaving D on the device. With the
@@ -558,10 +635,6 @@ void destroy(imin_graph *g)
     delete g;
 }
 
-// Workgroup-kernel slots given to a graph whose samples first outgrow the wave kernel
-// inside a batched call (a graph that already has scratch keeps it).
-constexpr int32_t kBatchSlots = 64;
-
 // A batched call runs every graph's work on one stream; each graph's own stream is put back
 // when the call ends, however it ends.
 struct StreamSwap {
@@ -592,14 +665,16 @@ struct BatchItem {
     int32_t rounds = 0;
 };
 
-// Scratch for a graph's first spilled samples of a batched call.
-int batch_workspace(imin_graph *g)
-{
-    if (g->main_ws.slots > 0) return IMIN_OK;
-    return size_workspaces(g, kBatchSlots);
-}
+// Frees a many-instance scratch when the call ends, however it ends.
+struct MultiScratchGuard {
+    MultiScratch s;
+    ~MultiScratchGuard() { multi_free(s); }
+};
 
-}  // namespace
+}  // namespace host
+}  // namespace imin
+
+using namespace imin::host;
 
 extern "C" {
 
@@ -1007,11 +1082,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
     for (int32_t i = 0; i < count; ++i) {
         BatchItem &it = items[(size_t)i];
         imin_graph *g = it.g;
-        int rc = ensure_ovf(g, it.in->theta);
-        if (rc) return rc;
-        rc = ensure_sj(g, it.in->theta);
-        if (rc) return rc;
-        rc = ensure_B(g, it.rounds);
+        const int rc = ensure_B(g, it.rounds);
         if (rc) return rc;
         describe(g, (int32_t)it.seeds.size(), it.in->seed, it.in->theta);
         table[(size_t)i] = g->h_inst;
@@ -1040,14 +1111,20 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
     DeviceBuf<imin::InstanceDesc> d_table;
     DeviceBuf<imin::BatchStage> d_stages;
     DeviceBuf<int32_t> d_stage, d_rounds, d_out;
-    DeviceBuf<uint32_t> d_si, d_sj, d_ctrl;
     if (!d_table.alloc((size_t)count) || !d_stages.alloc((size_t)count) ||
         !d_stage.alloc(stage.size()) || !d_rounds.alloc((size_t)count) ||
-        !d_out.alloc((size_t)count * stride) || !d_si.alloc(theta_sum) ||
-        !d_sj.alloc(theta_sum) || !d_ctrl.alloc(3)) {
+        !d_out.alloc((size_t)count * stride)) {
         (void)hipGetLastError();
         return IMIN_ENOMEM;
     }
+    int64_t max_n = 0, max_m = 0;
+    for (const BatchItem &it : items) {
+        max_n = std::max<int64_t>(max_n, it.g->n);
+        max_m = std::max<int64_t>(max_m, it.g->m);
+    }
+    MultiScratchGuard ms;
+    int rc = multi_alloc(ms.s, g0->num_cus, max_n, max_m, prefix[(size_t)count], bs);
+    if (rc) return rc;
     if (!ok(hipMemcpyAsync(d_table.p, table.data(), table.size() * sizeof(imin::InstanceDesc),
                            hipMemcpyHostToDevice, bs)) ||
         !ok(hipMemcpyAsync(d_stages.p, stages.data(), stages.size() * sizeof(imin::BatchStage),
@@ -1056,92 +1133,33 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
                            hipMemcpyHostToDevice, bs)) ||
         !ok(hipMemcpyAsync(d_rounds.p, rounds.data(), rounds.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, bs)) ||
-        !ok(imin::launch_batch_setup(d_table.p, d_stages.p, d_stage.p, count, bs)) ||
-        !ok(imin::launch_fill_u32(d_ctrl.p, 3, 0, bs)))
+        !ok(imin::launch_batch_setup(d_table.p, d_stages.p, d_stage.p, count, bs)))
         return IMIN_EDEVICE;
-    int rc = IMIN_OK;
+    // Rounds: every launch is queued at once; nothing waits for the host until the end.
     int32_t active = count;
-    std::vector<uint32_t> spill_i, spill_j, counts((size_t)count, 0u);
-    std::vector<std::vector<uint32_t>> lists((size_t)count);
     for (int32_t r = 0; r < max_rounds; ++r) {
         while (active > 0 && items[(size_t)active - 1].rounds <= r) --active;
         hipEvent_t k0, k1;
         rc = kernel_events(g0, &k0, &k1);
         if (rc) return rc;
-        if (!ok(imin::launch_batch_zero(d_table.p, active, bs)) ||
-            !ok(imin::launch_fill_u32(d_ctrl.p, 2, 0, bs)) || !ok(hipEventRecord(k0, bs)))
-            return IMIN_EDEVICE;
-        imin::SmallArgs s;
-        std::memset(&s, 0, sizeof(s));
-        s.inst = d_table.p;
-        s.ninst = active;
-        s.total = prefix[(size_t)active];
-        s.round = (uint32_t)r;
-        small_shape(s, shape);
-        s.next = d_ctrl.p + 0;
-        s.spill_inst = d_si.p;
-        s.spill_j = d_sj.p;
-        s.spill_count = d_ctrl.p + 1;
-        s.error = d_ctrl.p + 2;
-        if (!ok(imin::launch_decrease_small(s, small_grid(g0->num_cus, shape), bs)) ||
-            !ok(hipEventRecord(k1, bs)))
-            return IMIN_EDEVICE;
-        uint32_t nspill = 0;
-        if (!ok(hipMemcpyAsync(&nspill, d_ctrl.p + 1, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                               bs)) ||
-            !ok(hipStreamSynchronize(bs)))
-            return IMIN_EDEVICE;
-        if (nspill > 0) {
-            spill_i.resize(nspill);
-            spill_j.resize(nspill);
-            if (!ok(hipMemcpyAsync(spill_i.data(), d_si.p, nspill * sizeof(uint32_t),
-                                   hipMemcpyDeviceToHost, bs)) ||
-                !ok(hipMemcpyAsync(spill_j.data(), d_sj.p, nspill * sizeof(uint32_t),
-                                   hipMemcpyDeviceToHost, bs)) ||
-                !ok(hipStreamSynchronize(bs)))
-                return IMIN_EDEVICE;
-            for (auto &l : lists) l.clear();
-            for (uint32_t k = 0; k < nspill; ++k) {
-                if (spill_i[k] >= (uint32_t)active) return IMIN_EDEVICE;
-                lists[spill_i[k]].push_back(spill_j[k]);
-            }
-            hipEvent_t w0, w1;
-            rc = kernel_events(g0, &w0, &w1);
-            if (rc) return rc;
-            if (!ok(hipEventRecord(w0, bs))) return IMIN_EDEVICE;
-            for (int32_t i = 0; i < active; ++i) {
-                std::vector<uint32_t> &l = lists[(size_t)i];
-                if (l.empty()) continue;
-                BatchItem &it = items[(size_t)i];
-                imin_graph *g = it.g;
-                rc = batch_workspace(g);
-                if (rc) return rc;
-                counts[(size_t)i] = (uint32_t)l.size();
-                // The wave kernel left these samples untouched. The host lists and counts
-                // stay alive until the wait of the next round.
-                if (!ok(hipMemcpyAsync(g->d_sj, l.data(), l.size() * sizeof(uint32_t),
-                                       hipMemcpyHostToDevice, bs)) ||
-                    !ok(hipMemcpyAsync(g->d_sctrl + 1, &counts[(size_t)i], sizeof(uint32_t),
-                                       hipMemcpyHostToDevice, bs)))
-                    return IMIN_EDEVICE;
-                rc = launch_large(g, (int32_t)it.seeds.size(), it.in->theta,
-                                  it.in->seed + (uint64_t)r, g->d_sj, g->d_sctrl + 1);
-                if (rc) return rc;
-            }
-            if (!ok(hipEventRecord(w1, bs))) return IMIN_EDEVICE;
-        }
-        if (!ok(imin::launch_batch_argmax(d_table.p, active, r, bs))) return IMIN_EDEVICE;
+        if (!ok(hipEventRecord(k0, bs))) return IMIN_EDEVICE;
+        rc = multi_round(ms.s, d_table.p, active, prefix[(size_t)active], (uint32_t)r, shape,
+                         g0->num_cus, true, r, bs);
+        if (rc) return rc;
+        if (!ok(hipEventRecord(k1, bs))) return IMIN_EDEVICE;
     }
     // Results: every graph's blocker slots, counters and error flag, gathered into one
     // buffer, then one copy and one wait.
     std::vector<int32_t> out((size_t)count * stride);
-    uint32_t berr[3] = {0, 0, 0};
     if (!ok(imin::launch_batch_gather(d_table.p, d_rounds.p, d_out.p, stride, count, bs)) ||
         !ok(hipMemcpyAsync(out.data(), d_out.p, out.size() * sizeof(int32_t),
                            hipMemcpyDeviceToHost, bs)) ||
-        !ok(hipMemcpyAsync(berr, d_ctrl.p, sizeof(berr), hipMemcpyDeviceToHost, bs)) ||
         !ok(hipEventRecord(g0->ev1, bs)) || !ok(hipEventSynchronize(g0->ev1)))
         return IMIN_EDEVICE;
+    uint32_t wave_err = 0, wg_err = 0;
+    rc = multi_errors(ms.s, &wave_err, &wg_err, bs);
+    if (rc) return rc;
+    if (wave_err || wg_err) return IMIN_EDEVICE;
     std::vector<std::vector<int32_t>> B((size_t)count);
     std::vector<std::array<unsigned long long, kStats>> st((size_t)count);
     std::vector<uint32_t> err((size_t)count);
@@ -1153,7 +1171,6 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         err[(size_t)i] = (uint32_t)o[12];
         B[(size_t)i].assign(o + 13, o + 13 + items[(size_t)i].rounds);
     }
-    if (berr[2] != 0) return IMIN_EDEVICE;
     float total_ms = 0.0f;
     if (!ok(hipEventElapsedTime(&total_ms, g0->ev0, g0->ev1))) return IMIN_EDEVICE;
     double kms = 0.0;

@@ -25,6 +25,9 @@
 //
 // A sample whose scratch overflows is recorded and re-run by a second launch with
 // large-capacity slots; its partial work is discarded, so results never depend on that.
+// A launch serves one problem, or many (batched calls, the query server): then every
+// sample of its list names its instance, whose graph, thresholds, seeds, key and counters
+// replace the launch's own.
 #include "imin_internal.h"
 #include "philox.h"
 
@@ -55,6 +58,18 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *tot
     __syncthreads();
     return off + x - v;
 }
+
+// The problem one sample belongs to.
+struct Call {
+    const int32_t *row_ptr;
+    const uint4 *col4;
+    const uint4 *thr4;
+    const int32_t *seeds;
+    int32_t nseeds;
+    uint32_t key_lo, key_hi;
+    unsigned long long *D;
+    unsigned long long *stats;
+};
 
 struct SlotView {
     SlotEntry *map;
@@ -140,9 +155,9 @@ __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView
 // the edge quads of a chunk are spread evenly over the workgroup, two independent quads in
 // flight per thread. A quad's thresholds are always read; its targets only when one of its
 // coins comes up live.
-__device__ void expand(const DecreaseArgs &a, const SlotView &sv, Shared &sh, bool from_seeds,
-                       int lo, int hi, uint32_t j, uint32_t epoch, uint32_t &scanned,
-                       uint32_t &live)
+__device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv, Shared &sh,
+                       bool from_seeds, int lo, int hi, uint32_t j, uint32_t epoch,
+                       uint32_t &scanned, uint32_t &live)
 {
     const int tid = threadIdx.x;
     for (int base = lo; base < hi; base += kChunk) {
@@ -154,9 +169,9 @@ __device__ void expand(const DecreaseArgs &a, const SlotView &sv, Shared &sh, bo
             const int k = base + first + i;
             nq[i] = 0;
             if (k < hi) {
-                const int v = from_seeds ? a.seeds[k] : sv.loc[k].glob;
-                const int e0 = a.row_ptr[v];
-                const int e1 = a.row_ptr[v + 1];
+                const int v = from_seeds ? c.seeds[k] : sv.loc[k].glob;
+                const int e0 = c.row_ptr[v];
+                const int e1 = c.row_ptr[v + 1];
                 scanned += (uint32_t)(e1 - e0);
                 nq[i] = (e1 > e0) ? (((e1 - 1) >> 2) - (e0 >> 2) + 1) : 0;
                 sh.e0[first + i] = e0;
@@ -179,13 +194,13 @@ __device__ void expand(const DecreaseArgs &a, const SlotView &sv, Shared &sh, bo
             int l1, quad1, l2, quad2;
             locate(sh, cnt, q, l1, quad1);
             locate(sh, cnt, has2 ? q2 : q, l2, quad2);
-            const uint4 t1 = a.thr4[quad1];
-            const uint4 t2 = a.thr4[quad2];
-            const uint32_t m1 = live_mask(quad1, j, a.key_lo, a.key_hi, sh.e0[l1], sh.e1[l1], t1);
-            const uint32_t m2 = has2 ? live_mask(quad2, j, a.key_lo, a.key_hi, sh.e0[l2], sh.e1[l2], t2) : 0u;
+            const uint4 t1 = c.thr4[quad1];
+            const uint4 t2 = c.thr4[quad2];
+            const uint32_t m1 = live_mask(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], t1);
+            const uint32_t m2 = has2 ? live_mask(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], t2) : 0u;
             uint4 c1 = make_uint4(0, 0, 0, 0), c2 = make_uint4(0, 0, 0, 0);
-            if (m1) c1 = a.col4[quad1];
-            if (m2) c2 = a.col4[quad2];
+            if (m1) c1 = c.col4[quad1];
+            if (m2) c2 = c.col4[quad2];
             visit_mask(a, sv, sh, m1, c1, from_seeds ? 0 : base + l1, epoch, live);
             visit_mask(a, sv, sh, m2, c2, from_seeds ? 0 : base + l2, epoch, live);
         }
@@ -210,6 +225,7 @@ __device__ __forceinline__ void wave_add(unsigned *dst, uint32_t v)
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
 }
 
+template <bool kMulti>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void decrease_kernel(DecreaseArgs a)
 {
@@ -217,7 +233,7 @@ void decrease_kernel(DecreaseArgs a)
     const int tid = threadIdx.x;
     const size_t slot = blockIdx.x;
     SlotView sv;
-    sv.map = a.ws.map + slot * (size_t)a.n;
+    sv.map = a.ws.map + slot * (size_t)a.ws.n;
     sv.loc = a.ws.loc + slot * (size_t)a.ws.lcap;
     sv.lvl = a.ws.lvl + slot * (size_t)(a.ws.lcap + 1);
     sv.extra = a.ws.extra + slot * (size_t)a.ws.xcap;
@@ -230,6 +246,18 @@ void decrease_kernel(DecreaseArgs a)
         const uint32_t idx = sh.idx;
         if (idx >= count) break;
         const uint32_t j = a.sample_list ? a.sample_list[idx] : idx;
+        // This sample's problem: the launch's own, or an instance of a many-instance launch
+        // (all instances' vertex ids fit the slot maps).
+        Call c{a.row_ptr, a.col4, a.thr4, a.seeds, a.nseeds, a.key_lo, a.key_hi, a.D, a.stats};
+        uint32_t inst_i = 0;
+        if (kMulti) {
+            inst_i = __builtin_amdgcn_readfirstlane(a.sample_inst[idx]);
+            const InstanceDesc &I = a.inst[inst_i];
+            const unsigned long long key =
+                (((unsigned long long)I.seed_hi << 32) | I.seed_lo) + a.round;
+            c = Call{I.row_ptr, I.col4, I.thr4,        I.seeds, I.nseeds,
+                     (uint32_t)key, (uint32_t)(key >> 32), I.D, I.stats};
+        }
         ++epoch;
         if (tid == 0) {
             sh.tail = 1;
@@ -249,14 +277,14 @@ void decrease_kernel(DecreaseArgs a)
         __syncthreads();
 
         uint32_t p_scanned = 0, p_live = 0;
-        expand(a, sv, sh, true, 0, a.nseeds, j, epoch, p_scanned, p_live);
+        expand(a, c, sv, sh, true, 0, c.nseeds, j, epoch, p_scanned, p_live);
         int L = 1, lo = 1;
         int hi = sh.tail;
         __syncthreads();
         while (lo < hi) {
             if (sh.ovf) break;
             if (tid == 0) sv.lvl[L + 1] = hi;
-            expand(a, sv, sh, false, lo, hi, j, epoch, p_scanned, p_live);
+            expand(a, c, sv, sh, false, lo, hi, j, epoch, p_scanned, p_live);
             lo = hi;
             hi = sh.tail;
             ++L;
@@ -267,7 +295,8 @@ void decrease_kernel(DecreaseArgs a)
                 if (a.spill_ok) {
                     const uint32_t pos = atomicAdd(a.ovf_count, 1u);
                     a.ovf_list[pos] = j;
-                    atomicAdd(&a.stats[4], 1ull);
+                    if (kMulti) a.ovf_inst[pos] = inst_i;
+                    atomicAdd(&c.stats[4], 1ull);
                 } else {
                     atomicOr(a.error, 1u);
                 }
@@ -335,15 +364,15 @@ void decrease_kernel(DecreaseArgs a)
                 if (r.tdom != 0)
                     __hip_atomic_fetch_add(&sv.loc[r.tdom].csz, r.csz, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
-                atomicAdd(&a.D[r.glob], (unsigned long long)r.csz);
+                atomicAdd(&c.D[r.glob], (unsigned long long)r.csz);
             }
             __syncthreads();
         }
         if (tid == 0) {
-            atomicAdd(&a.stats[0], 1ull);
-            atomicAdd(&a.stats[1], (unsigned long long)(nV - 1));
-            atomicAdd(&a.stats[2], (unsigned long long)sh.scanned);
-            atomicAdd(&a.stats[3], (unsigned long long)sh.live);
+            atomicAdd(&c.stats[0], 1ull);
+            atomicAdd(&c.stats[1], (unsigned long long)(nV - 1));
+            atomicAdd(&c.stats[2], (unsigned long long)sh.scanned);
+            atomicAdd(&c.stats[3], (unsigned long long)sh.live);
         }
     }
     if (tid == 0) a.ws.epoch[slot] = epoch;
@@ -354,7 +383,10 @@ void decrease_kernel(DecreaseArgs a)
 hipError_t launch_decrease(const DecreaseArgs &a, hipStream_t stream)
 {
     if (a.ws.slots <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(decrease_kernel, dim3(a.ws.slots), dim3(kBlock), 0, stream, a);
+    if (a.inst)
+        hipLaunchKernelGGL(decrease_kernel<true>, dim3(a.ws.slots), dim3(kBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL(decrease_kernel<false>, dim3(a.ws.slots), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -35,6 +35,7 @@ struct LocalVtx {
 // [s * n, (s + 1) * n) of `map`, [s * lcap, (s + 1) * lcap) of `loc`, and so on.
 struct Workspace {
     int32_t slots = 0;
+    int64_t n = 0;             // map entries per slot (vertex ids below n)
     int64_t lcap = 0;          // local vertices per sample (root included)
     int64_t xcap = 0;          // non-tree live edges per sample
     SlotEntry *map = nullptr;  // slots * n
@@ -45,6 +46,8 @@ struct Workspace {
     uint64_t epochs_used = 0;  // host-side bound on the largest epoch issued so far
     size_t bytes = 0;
 };
+
+struct InstanceDesc;
 
 // Everything one launch of the decrease kernel reads or writes.
 struct DecreaseArgs {
@@ -67,7 +70,14 @@ struct DecreaseArgs {
     uint32_t *error;         // set when a sample overflows with spill_ok == 0
     int32_t spill_ok;
     int32_t reach_only;      // count reached vertices only (spread estimates)
-    Workspace ws;
+    Workspace ws;            // slot maps of `n` entries
+    // Many-instance launches (inst non-null): sample idx is sample sample_list[idx] of
+    // instance inst[sample_inst[idx]] with key seed + round; overflowing samples are
+    // listed with their instance in ovf_inst. Every instance's n must be <= n.
+    const InstanceDesc *inst;
+    const uint32_t *sample_inst;
+    uint32_t *ovf_inst;
+    uint32_t round;
 };
 
 // decrease.hip
