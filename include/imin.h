@@ -221,6 +221,67 @@ typedef struct {
 IMIN_API int imin_greedy_batch(imin_instance *inst, int32_t count, int mode,
                                const imin_launch *launch);
 
+/*
+ * Query server: AdvancedGreedy for a stream of queries against one resident graph, with
+ * continuous batching (see imin_server_step). A query's blockers and counters are those of
+ * imin_greedy(g, S, nS, b, theta, seed, IMIN_AG) alone, whatever else runs beside it.
+ */
+typedef struct imin_server imin_server;
+
+typedef struct {
+    uint64_t hbm_budget;  /* device bytes for per-query state (0: a quarter of free memory) */
+    int32_t max_active;   /* most queries admitted at once (0: 256) */
+    uint32_t max_theta;   /* largest theta a query may ask for (0: 65536); max_active *
+                             max_theta must not exceed 2^31 (IMIN_ERANGE) */
+    imin_launch launch;   /* wave-kernel launch shape (zeros: defaults) */
+} imin_server_config;
+
+/*
+ * imin_server_create -- a server for graph g (cfg may be NULL for defaults). The server
+ * reads g's resident arrays and never changes them; g must outlive the server. Errors:
+ * IMIN_EINVAL, IMIN_ERANGE, IMIN_ENOMEM (budget or scratch not allocatable), IMIN_EDEVICE.
+ */
+IMIN_API int imin_server_create(imin_graph *g, const imin_server_config *cfg, imin_server **out);
+
+/* Release a server and its device memory (pending queries are dropped). NULL is ignored. */
+IMIN_API void imin_server_destroy(imin_server *s);
+
+/* Device bytes a query with nS distinct seeds and budget b holds while admitted. */
+IMIN_API int imin_server_query_bytes(const imin_server *s, int32_t nS, int32_t b,
+                                     uint64_t *bytes);
+
+/*
+ * imin_server_submit -- queue a query (arguments as for imin_greedy with IMIN_AG) and
+ * receive its ticket. Nothing runs until imin_server_step. Errors: IMIN_EINVAL as for
+ * imin_greedy; IMIN_ERANGE when theta > max_theta or the query's state can never fit the
+ * budget.
+ */
+IMIN_API int imin_server_submit(imin_server *s, const int32_t *S, int32_t nS, int32_t b,
+                                uint32_t theta, uint64_t seed, uint64_t *ticket);
+
+/*
+ * imin_server_step -- one scheduling step: admit queued queries in arrival order while
+ * their state fits the budget and fewer than max_active are admitted (a query that does
+ * not fit waits, and so do the ones behind it); run one greedy round of every admitted
+ * query in shared launches; retire the queries whose rounds are done. Returns when the
+ * step's GPU work has finished. n_active / n_queued (nullable) receive the counts after
+ * the step.
+ */
+IMIN_API int imin_server_step(imin_server *s, int32_t *n_active, int32_t *n_queued);
+
+/* Pop up to cap tickets of queries finished since the last call, oldest first. */
+IMIN_API int imin_server_completed(imin_server *s, uint64_t *tickets, int32_t cap,
+                                   int32_t *count);
+
+/*
+ * imin_server_result -- take a finished query's blockers (capacity cap) and counters
+ * (device_ms and kernel_ms are 0). Returns IMIN_OK once, then forgets the ticket; 1 while
+ * the query is queued or running; IMIN_EINVAL for an unknown ticket; IMIN_ERANGE when cap is
+ * too small (the result stays available).
+ */
+IMIN_API int imin_server_result(imin_server *s, uint64_t ticket, int32_t *blockers, int32_t cap,
+                                int32_t *n_blockers, imin_stats *stats);
+
 /* Human-readable text of a status code (static storage). */
 IMIN_API const char *imin_strerror(int status);
 

@@ -2,7 +2,8 @@
 
 The functions keep the C names (``imin_graph_create``, ``imin_decrease``, ``imin_spread``,
 ``imin_greedy``, ``imin_greedy_batch``, ``imin_set_launch``, ``imin_set_small``,
-``imin_graph_destroy``, ``imin_strerror``); ``Graph`` wraps them for convenience. Every step
+``imin_graph_destroy``, ``imin_server_*``, ``imin_strerror``); ``Graph`` and ``Server`` wrap
+them for convenience. Every step
 of the estimate runs in the library's HIP kernels; if the library is missing this module
 raises instead of computing anything itself.
 """
@@ -50,6 +51,11 @@ def _launch(launch):
     return ctypes.byref(imin_launch(**{k: int(v) for k, v in launch.items()}))
 
 
+class imin_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_active", ctypes.c_int32),
+                ("max_theta", ctypes.c_uint32), ("launch", imin_launch)]
+
+
 class imin_instance(ctypes.Structure):
     _fields_ = [("g", ctypes.c_void_p), ("S", ctypes.c_void_p), ("nS", ctypes.c_int32),
                 ("b", ctypes.c_int32), ("theta", ctypes.c_uint32), ("seed", ctypes.c_uint64),
@@ -93,6 +99,25 @@ def load() -> ctypes.CDLL:
     lib.imin_greedy_batch.argtypes = [ctypes.POINTER(imin_instance), ctypes.c_int32,
                                       ctypes.c_int, P]
     lib.imin_greedy_batch.restype = ctypes.c_int
+    lib.imin_server_create.argtypes = [P, ctypes.POINTER(imin_server_config),
+                                       ctypes.POINTER(ctypes.c_void_p)]
+    lib.imin_server_create.restype = ctypes.c_int
+    lib.imin_server_destroy.argtypes = [P]
+    lib.imin_server_destroy.restype = None
+    lib.imin_server_query_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_uint64)]
+    lib.imin_server_query_bytes.restype = ctypes.c_int
+    lib.imin_server_submit.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
+                                       ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.imin_server_submit.restype = ctypes.c_int
+    lib.imin_server_step.argtypes = [P, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]
+    lib.imin_server_step.restype = ctypes.c_int
+    lib.imin_server_completed.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.imin_server_completed.restype = ctypes.c_int
+    lib.imin_server_result.argtypes = [P, ctypes.c_uint64, P, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(imin_stats)]
+    lib.imin_server_result.restype = ctypes.c_int
     lib.imin_strerror.argtypes = [ctypes.c_int]
     lib.imin_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -243,6 +268,87 @@ class Graph:
 
     def __exit__(self, *exc):
         self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A query server on a resident graph (``imin_server_*``): submit (S, b, theta, seed)
+    AdvancedGreedy queries, drive it with ``step``, collect finished ones."""
+
+    def __init__(self, graph: Graph, hbm_budget: int = 0, max_active: int = 0,
+                 max_theta: int = 0, launch=None):
+        cfg = imin_server_config()
+        cfg.hbm_budget = int(hbm_budget)
+        cfg.max_active = int(max_active)
+        cfg.max_theta = int(max_theta)
+        if launch:
+            for k, v in launch.items():
+                setattr(cfg.launch, k, int(v))
+        h = ctypes.c_void_p()
+        rc = load().imin_server_create(ctypes.c_void_p(graph.handle), ctypes.byref(cfg),
+                                       ctypes.byref(h))
+        if rc != IMIN_OK:
+            raise IminError("imin_server_create", rc)
+        self.handle = h.value
+        self.graph = graph  # the graph must outlive the server
+
+    def query_bytes(self, n_seeds: int, b: int) -> int:
+        out = ctypes.c_uint64()
+        rc = load().imin_server_query_bytes(ctypes.c_void_p(self.handle), int(n_seeds), int(b),
+                                            ctypes.byref(out))
+        if rc != IMIN_OK:
+            raise IminError("imin_server_query_bytes", rc)
+        return out.value
+
+    def submit(self, seeds, b: int, theta: int, seed: int = 0) -> int:
+        S = np.ascontiguousarray(seeds, dtype=np.int32)
+        t = ctypes.c_uint64()
+        rc = load().imin_server_submit(ctypes.c_void_p(self.handle), _p(S), S.shape[0], int(b),
+                                       int(theta), int(seed) & (2**64 - 1), ctypes.byref(t))
+        if rc != IMIN_OK:
+            raise IminError("imin_server_submit", rc)
+        return t.value
+
+    def step(self):
+        """One scheduling step; returns (active, queued) after it."""
+        a, q = ctypes.c_int32(), ctypes.c_int32()
+        rc = load().imin_server_step(ctypes.c_void_p(self.handle), ctypes.byref(a),
+                                     ctypes.byref(q))
+        if rc != IMIN_OK:
+            raise IminError("imin_server_step", rc)
+        return a.value, q.value
+
+    def completed(self, cap: int = 4096):
+        out = np.zeros(cap, dtype=np.uint64)
+        k = ctypes.c_int32()
+        rc = load().imin_server_completed(ctypes.c_void_p(self.handle), _p(out), int(cap),
+                                          ctypes.byref(k))
+        if rc != IMIN_OK:
+            raise IminError("imin_server_completed", rc)
+        return [int(x) for x in out[: k.value]]
+
+    def result(self, ticket: int, cap: int):
+        """(blockers, stats dict) of a finished query, or None while it is pending."""
+        out = np.zeros(max(int(cap), 1), dtype=np.int32)
+        nb = ctypes.c_int32()
+        st = imin_stats()
+        rc = load().imin_server_result(ctypes.c_void_p(self.handle), int(ticket), _p(out),
+                                       int(cap), ctypes.byref(nb), ctypes.byref(st))
+        if rc == 1:
+            return None
+        if rc != IMIN_OK:
+            raise IminError("imin_server_result", rc)
+        return out[: nb.value].copy(), st.as_dict()
+
+    def close(self) -> None:
+        if self.handle:
+            load().imin_server_destroy(ctypes.c_void_p(self.handle))
+            self.handle = 0
 
     def __del__(self):
         try:
