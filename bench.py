@@ -164,6 +164,76 @@ def bench_batched(args) -> dict:
     return out
 
 
+def bench_served(args) -> dict:
+    import numpy as np
+    import torch
+    from paper_2302_13529_amd import binding, graphgen as gg, serve
+
+    print("[bench] generating the served graph and queries", file=sys.stderr, flush=True)
+    inst = gg.served_graph()
+    queries = gg.served_queries(inst.n)[: args.queries]
+    g = binding.Graph(inst.row_ptr, inst.col, inst.prob)
+    budget = int(args.hbm_gib * (1 << 30))
+    srv = binding.Server(g, hbm_budget=budget, max_active=args.max_active, max_theta=10000)
+    # plain form: one imin_greedy call per query, on a bounded prefix of the mix
+    plain_n = min(args.plain_queries, len(queries))
+    print(f"[bench] plain: warmup + {plain_n} queries", file=sys.stderr, flush=True)
+    q0 = queries[0]
+    g.greedy(q0["seeds"], 2, q0["theta"], q0["seed"], binding.IMIN_AG)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [g.greedy(q["seeds"], q["b"], q["theta"], q["seed"], binding.IMIN_AG)
+             for q in queries[:plain_n]]
+    plain_s = time.perf_counter() - t0
+    plain_samples = sum(st["samples"] for _, st in plain)
+    plain_qps = plain_n / plain_s
+    # served, saturated: every query submitted at time 0
+    print(f"[bench] served, saturated: {len(queries)} queries", file=sys.stderr, flush=True)
+    res, lat_sat, span, steps = serve.run(srv, queries)
+    served_samples = sum(st["samples"] for _, st in res)
+    identical = all(list(res[i][0]) == list(plain[i][0]) and
+                    res[i][1]["reached"] == plain[i][1]["reached"] for i in range(plain_n))
+    # served, Poisson arrivals at 0.8x the plain form's query rate
+    rate = 0.8 * plain_qps
+    arrivals = serve.poisson_arrivals(len(queries), rate, seed=7)
+    print(f"[bench] served, Poisson arrivals at {rate:.2f} queries/s", file=sys.stderr,
+          flush=True)
+    res2, lat, span2, steps2 = serve.run(srv, queries, arrivals)
+    identical = identical and all(list(a[0]) == list(b[0]) for a, b in zip(res, res2))
+    srv.close()
+    g.close()
+    out = {
+        "metric": "live-edge samples/sec incl. dominator decrease",
+        "value": served_samples / span,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 1,
+        "ms_per_step": span * 1e3 / max(steps, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": inst.name, "n": inst.n, "m": inst.m, "queries": len(queries),
+                   "step": "one server step: a greedy round of every admitted query",
+                   "hbm_budget_gib": args.hbm_gib, "max_active": args.max_active,
+                   "parallelism": "none"},
+        "plain_value": plain_samples / plain_s,
+        "plain_queries": plain_n,
+        "speedup_vs_plain": (served_samples / span) / (plain_samples / plain_s),
+        "identical_to_plain": identical,
+        "saturated_makespan_s": span,
+        "poisson_rate_qps": rate,
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "poisson_makespan_s": span2,
+        "queries_per_s_served": len(queries) / span,
+        "queries_per_s_plain": plain_qps,
+    }
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,7 +241,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-samples", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["rmat22", "batched"], default="rmat22")
+    ap.add_argument("--workload", choices=["rmat22", "batched", "served"], default="rmat22")
+    ap.add_argument("--queries", type=int, default=2000, help="served: queries of the mix")
+    ap.add_argument("--plain-queries", type=int, default=40,
+                    help="served: queries timed one plain call at a time")
+    ap.add_argument("--hbm-gib", type=float, default=16.0, help="served: query-state budget")
+    ap.add_argument("--max-active", type=int, default=128, help="served: admitted at once")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--quad-limit", type=int, default=0)
     ap.add_argument("--pick-div", type=int, default=0)
@@ -185,6 +260,9 @@ def main() -> int:
         return 2
     if args.workload == "batched":
         print(json.dumps(bench_batched(args)), flush=True)
+        return 0
+    if args.workload == "served":
+        print(json.dumps(bench_served(args)), flush=True)
         return 0
 
     import torch

@@ -181,8 +181,9 @@ typedef struct {
  * more than 255 vertices, keeps more than 256 non-tree live edges, or meets a frontier
  * chunk over the quad limit is left, with nothing accumulated, to the one-workgroup-per-
  * sample kernel in the same call.
- *   enable  -1 automatic (the default: on, and switched off for g once fewer than half of
- *           a round's samples finish in the wave kernel), 0 off, 1 on.
+ *   enable  -1 automatic (the default: on for the first round of every call, and off for
+ *           the call's later rounds when fewer than half of the first round's samples
+ *           finished in the wave kernel), 0 off, 1 on.
  *   launch  the wave kernel's launch shape (NULL: defaults).
  * Results never depend on these values. Errors: IMIN_EINVAL for NULL g, enable outside
  * [-1, 1], or negative launch values.

@@ -391,8 +391,15 @@ int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uin
     const int64_t lcap = max_n + 1;
     const int64_t xmax = max_m + 1;
     const int64_t xcap = std::min<int64_t>(std::max<int64_t>(4096, lcap / 4), xmax);
-    // one workgroup slot per compute unit: samples that outgrow the wave kernel are few
-    int rc = alloc_ws(ms.main_ws, max_n, std::max(1, num_cus), lcap, xcap, stream);
+    // two workgroup slots per compute unit, as single calls use, within a quarter of the
+    // free memory
+    size_t free_b = 0, total_b = 0;
+    if (!ok(hipMemGetInfo(&free_b, &total_b))) return IMIN_EDEVICE;
+    free_b += ms.main_ws.bytes;
+    const size_t per = slot_bytes(max_n, lcap, xcap);
+    const int32_t slots = (int32_t)std::max<size_t>(
+        1, std::min<size_t>((size_t)2 * std::max(1, num_cus), (free_b / 4) / per));
+    int rc = alloc_ws(ms.main_ws, max_n, slots, lcap, xcap, stream);
     if (rc) return rc;
     if (xcap < xmax) {
         rc = alloc_ws(ms.big_ws, max_n, (int32_t)kSpillSlots, lcap, xmax, stream);
@@ -577,8 +584,9 @@ int finish_call(imin_graph *g, imin_stats *stats)
     return IMIN_OK;
 }
 
-// Automatic wave-kernel policy: after a graph's first round with the wave kernel on, keep
-// it only if it finished most of the samples (the results are the same either way).
+// Automatic wave-kernel policy: after a call's first round with the wave kernel on, keep it
+// for the call's later rounds only if it finished most of the samples (the results are the
+// same either way).
 int auto_check(imin_graph *g)
 {
     if (g->small_mode != -1 || g->small_auto_off) return IMIN_OK;
@@ -596,6 +604,7 @@ int begin_call(imin_graph *g)
 {
     if (!ok(hipSetDevice(g->device))) return IMIN_EDEVICE;
     g->kev_used = 0;
+    g->small_auto_off = false;  // every call tries the wave kernel in its first round
     if (!ok(hipEventRecord(g->ev0, g->stream))) return IMIN_EDEVICE;
     return IMIN_OK;
 }
@@ -845,7 +854,6 @@ int one_call(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *blocked
     if (rc) return rc;
     rc = upload_call_state(g, seeds, inelig, seed, theta);
     if (rc) return rc;
-    const bool small = small_enabled(g);
     rc = decrease_round(g, (int32_t)seeds.size(), theta, seed, 0, reach_only);
     if (rc) return rc;
     std::vector<unsigned long long> D;
@@ -859,9 +867,6 @@ int one_call(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *blocked
     rc = finish_call(g, &st);
     if (rc) return rc;
     end_masks(g, {});
-    if (small && g->small_mode == -1 &&
-        (double)st.wave_samples < kSmallKeepShare * (double)st.samples)
-        g->small_auto_off = true;
     if (!reach_only) std::memcpy(counts, D.data(), (size_t)g->n * sizeof(uint64_t));
     if (stats) *stats = st;
     *n_seeds = (int32_t)seeds.size();

@@ -37,7 +37,8 @@ struct imin_graph {
     imin::InstanceDesc *d_inst = nullptr;    // this graph as the one instance of a wave launch
     imin::InstanceDesc h_inst{};
     int small_mode = -1;                     // wave kernel: -1 automatic, 0 off, 1 on
-    bool small_auto_off = false;             // automatic mode found most samples too large
+    bool small_auto_off = false;             // automatic mode: this call's first round found
+                                             // most samples too large
     imin_launch small_launch{0, 0, 0};       // 0 fields: defaults
     uint32_t *d_ovf = nullptr;
     uint32_t ovf_cap = 0;
