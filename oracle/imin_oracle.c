@@ -27,6 +27,15 @@
  *     greedy drivers never depends on summation order.
  *   - AdvancedGreedy (Algorithm 3) and GreedyReplace (Algorithm 4); ties in the argmax go
  *     to the smallest vertex id, seeds are never candidates.
+ *   - Triggering model (Section V-E), as the linear-threshold instance: the weight w(v,u) of
+ *     each in-edge of u (sum over u's in-edges <= 1) is the probability that v alone forms
+ *     u's triggering set; with the remaining probability the set is empty. A sampled graph
+ *     keeps exactly the in-edge of u named by u's triggering set. u's choice in sample j:
+ *        R = Philox4x32_10(counter=(u>>2, j, 1, 0), key)[u & 3] >> 8
+ *        bound_k = min(2^24, ceil(2^24 * (w_1 + ... + w_k)))   (fp64 running sums over u's
+ *                  in-edges taken in ascending edge id; bound_0 = 0)
+ *        the in-edge e_k with bound_{k-1} <= R < bound_k, or none when R >= bound_last.
+ *     Everything downstream (dominators, counts, greedy) is unchanged.
  *
  * Parity pins live in tests/: Philox against torch's header-only engine, the coin rule
  * against the float test over all 2^24 values, dominators against networkx and against
@@ -42,6 +51,8 @@
 #define ORC_OK 0
 #define ORC_EINVAL (-1)
 #define ORC_ENOMEM (-2)
+#define ORC_IC 0
+#define ORC_LT 1
 
 /* ---------------------------------------------------------------- Philox4x32-10 */
 
@@ -100,12 +111,34 @@ int orc_edge_live(uint64_t key, uint32_t j, int64_t e, float p)
     return edge_live(key, j, e, orc_threshold(p));
 }
 
+/* LT: the in-edge of u chosen in sample j (its triggering set), or -1 for none. */
+static int64_t lt_trigger(const int32_t *in_ptr, const int32_t *in_edge, const float *w,
+                          uint64_t key, uint32_t j, int32_t u)
+{
+    uint32_t ctr[4] = {(uint32_t)u >> 2, j, 1u, 0u};
+    uint32_t k[2] = {(uint32_t)key, (uint32_t)(key >> 32)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, k, out);
+    const double R = (double)(out[u & 3] >> 8);
+    double sum = 0.0;
+    for (int32_t i = in_ptr[u]; i < in_ptr[u + 1]; ++i) {
+        sum += (double)w[in_edge[i]];
+        double bound = ceil(sum * 16777216.0);
+        if (bound > 16777216.0) bound = 16777216.0;
+        if (R < bound) return in_edge[i];
+    }
+    return -1;
+}
+
 /* ---------------------------------------------------------------- problem state */
 
 typedef struct {
     int32_t n;
     const int32_t *row_ptr;
     const int32_t *col;
+    int model;             /* ORC_IC or ORC_LT */
+    const float *w;        /* LT: edge weights */
+    int32_t *in_ptr, *in_edge; /* LT: in-edges of each vertex, ascending edge id */
     uint32_t *thr;         /* per edge */
     uint8_t *is_seed;      /* per vertex */
     const uint8_t *blocked;/* per vertex, may be NULL */
@@ -125,6 +158,13 @@ typedef struct {
     int32_t *size, *child_ptr, *child, *fill;
     uint64_t edges_scanned, live_edges;
 } orc_state;
+
+static int live_in_sample(const orc_state *st, uint64_t key, uint32_t j, int64_t e)
+{
+    if (st->model == ORC_LT)
+        return lt_trigger(st->in_ptr, st->in_edge, st->w, key, j, st->col[e]) == e;
+    return edge_live(key, j, e, st->thr[e]);
+}
 
 static int blocked_at(const orc_state *st, int32_t v)
 {
@@ -181,7 +221,7 @@ static int build_sample(orc_state *st, uint64_t key, uint32_t j)
         for (int64_t e = st->row_ptr[s]; e < st->row_ptr[s + 1]; ++e) {
             int32_t v = st->col[e];
             st->edges_scanned++;
-            if (!edge_live(key, j, e, st->thr[e])) continue;
+            if (!live_in_sample(st, key, j, e)) continue;
             if (!eligible(st, v)) continue;
             st->live_edges++;
             int32_t lv = visit(st, v);
@@ -193,7 +233,7 @@ static int build_sample(orc_state *st, uint64_t key, uint32_t j)
         for (int64_t e = st->row_ptr[u]; e < st->row_ptr[u + 1]; ++e) {
             int32_t v = st->col[e];
             st->edges_scanned++;
-            if (!edge_live(key, j, e, st->thr[e])) continue;
+            if (!live_in_sample(st, key, j, e)) continue;
             if (!eligible(st, v)) continue;
             st->live_edges++;
             int32_t lv = visit(st, v);
@@ -337,7 +377,7 @@ static void subtree_sizes(orc_state *st)
 
 static void state_free(orc_state *st)
 {
-    free(st->thr); free(st->is_seed); free(st->seeds);
+    free(st->thr); free(st->is_seed); free(st->seeds); free(st->in_ptr); free(st->in_edge);
     free(st->loc); free(st->glob); free(st->esrc); free(st->edst);
     free(st->succ_ptr); free(st->succ); free(st->pred_ptr); free(st->pred);
     free(st->num); free(st->vert); free(st->parent); free(st->semi); free(st->idom);
@@ -361,10 +401,38 @@ static int check_graph(int32_t n, const int32_t *row_ptr, const int32_t *col, co
     return ORC_OK;
 }
 
+/* In-edges of every vertex in ascending edge id (a counting sort by target). */
+static int build_in_edges(orc_state *st, int64_t m)
+{
+    int32_t n = st->n;
+    st->in_ptr = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    st->in_edge = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int32_t *fill = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!st->in_ptr || !st->in_edge || !fill) { free(fill); return ORC_ENOMEM; }
+    for (int64_t e = 0; e < m; ++e) st->in_ptr[st->col[e] + 1]++;
+    for (int32_t v = 0; v < n; ++v) st->in_ptr[v + 1] += st->in_ptr[v];
+    for (int32_t v = 0; v < n; ++v) fill[v] = st->in_ptr[v];
+    for (int64_t e = 0; e < m; ++e) st->in_edge[fill[st->col[e]]++] = (int32_t)e;
+    free(fill);
+    return ORC_OK;
+}
+
+/* LT weights: the in-edge weights of every vertex sum to at most 1 (up to fp32 rounding). */
+static int check_lt_weights(const orc_state *st)
+{
+    for (int32_t v = 0; v < st->n; ++v) {
+        double sum = 0.0;
+        for (int32_t i = st->in_ptr[v]; i < st->in_ptr[v + 1]; ++i) sum += st->w[st->in_edge[i]];
+        if (sum > 1.0 + 1e-5) return ORC_EINVAL;
+    }
+    return ORC_OK;
+}
+
 static int state_init(orc_state *st, int32_t n, const int32_t *row_ptr, const int32_t *col,
-                      const float *prob, const int32_t *S, int32_t nS)
+                      const float *prob, const int32_t *S, int32_t nS, int model)
 {
     memset(st, 0, sizeof(*st));
+    if (model != ORC_IC && model != ORC_LT) return ORC_EINVAL;
     int rc = check_graph(n, row_ptr, col, prob);
     if (rc) return rc;
     if (nS <= 0 || !S) return ORC_EINVAL;
@@ -392,6 +460,13 @@ static int state_init(orc_state *st, int32_t n, const int32_t *row_ptr, const in
         return ORC_ENOMEM;
     }
     for (int64_t e = 0; e < m; ++e) st->thr[e] = orc_threshold(prob[e]);
+    st->model = model;
+    st->w = prob;
+    if (model == ORC_LT) {
+        rc = build_in_edges(st, m);
+        if (!rc) rc = check_lt_weights(st);
+        if (rc) { state_free(st); return rc; }
+    }
     for (int32_t i = 0; i < nS; ++i) st->is_seed[S[i]] = 1;
     st->nseeds = 0;
     for (int32_t v = 0; v < n; ++v)
@@ -448,12 +523,12 @@ static int check_blocked(const orc_state *st)
  * idom_out[v] = global id of idom(v) (-1 for children of the merged source, -2 if v is
  * unreached or a seed). Returns |R_j| (reached non-seed vertices) or a negative error.
  */
-int64_t orc_sample(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
-                   const int32_t *S, int32_t nS, const uint8_t *blocked, uint64_t key,
-                   uint32_t j, int32_t *c_out, int32_t *idom_out)
+int64_t orc_sample_m(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
+                     const int32_t *S, int32_t nS, const uint8_t *blocked, uint64_t key,
+                     uint32_t j, int32_t *c_out, int32_t *idom_out, int model)
 {
     orc_state st;
-    int rc = state_init(&st, n, row_ptr, col, prob, S, nS);
+    int rc = state_init(&st, n, row_ptr, col, prob, S, nS, model);
     if (rc) return rc;
     st.blocked = blocked;
     rc = check_blocked(&st);
@@ -500,20 +575,53 @@ static int decrease_into(orc_state *st, uint32_t theta, uint64_t key, uint64_t *
     return ORC_OK;
 }
 
+int64_t orc_sample(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
+                   const int32_t *S, int32_t nS, const uint8_t *blocked, uint64_t key,
+                   uint32_t j, int32_t *c_out, int32_t *idom_out)
+{
+    return orc_sample_m(n, row_ptr, col, prob, S, nS, blocked, key, j, c_out, idom_out, ORC_IC);
+}
+
 /* Algorithm 2 with integer accumulation: counts[u] = sum over theta samples of c_j[u]. */
-int orc_decrease(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
-                 const int32_t *S, int32_t nS, const uint8_t *blocked, uint32_t theta,
-                 uint64_t key, uint64_t *counts, uint64_t *stats)
+int orc_decrease_m(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
+                   const int32_t *S, int32_t nS, const uint8_t *blocked, uint32_t theta,
+                   uint64_t key, uint64_t *counts, uint64_t *stats, int model)
 {
     if (theta == 0 || !counts) return ORC_EINVAL;
     orc_state st;
-    int rc = state_init(&st, n, row_ptr, col, prob, S, nS);
+    int rc = state_init(&st, n, row_ptr, col, prob, S, nS, model);
     if (rc) return rc;
     st.blocked = blocked;
     rc = check_blocked(&st);
     if (!rc) rc = decrease_into(&st, theta, key, counts, stats);
     state_free(&st);
     return rc;
+}
+
+int orc_decrease(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
+                 const int32_t *S, int32_t nS, const uint8_t *blocked, uint32_t theta,
+                 uint64_t key, uint64_t *counts, uint64_t *stats)
+{
+    return orc_decrease_m(n, row_ptr, col, prob, S, nS, blocked, theta, key, counts, stats,
+                          ORC_IC);
+}
+
+/* LT: the in-edge chosen by u in sample j under key (its triggering set), or -1. */
+int64_t orc_lt_trigger(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *w,
+                       uint64_t key, uint32_t j, int32_t u)
+{
+    if (u < 0 || u >= n) return ORC_EINVAL;
+    orc_state st;
+    memset(&st, 0, sizeof(st));
+    if (check_graph(n, row_ptr, col, w)) return ORC_EINVAL;
+    st.n = n;
+    st.row_ptr = row_ptr;
+    st.col = col;
+    st.w = w;
+    if (build_in_edges(&st, row_ptr[n])) { state_free(&st); return ORC_ENOMEM; }
+    int64_t e = lt_trigger(st.in_ptr, st.in_edge, w, key, j, u);
+    state_free(&st);
+    return e;
 }
 
 #define ORC_AG 0
@@ -528,10 +636,10 @@ int orc_decrease(int32_t n, const int32_t *row_ptr, const int32_t *col, const fl
  * blockers[] receives the slots in order; *n_blockers their count; calls_out the number
  * of calls of Algorithm 2 made; stats accumulate over all calls.
  */
-int orc_greedy(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
-               const int32_t *S, int32_t nS, int32_t b, uint32_t theta, uint64_t seed,
-               int32_t mode, int32_t *blockers, int32_t *n_blockers, int32_t *calls_out,
-               uint64_t *stats)
+int orc_greedy_m(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
+                 const int32_t *S, int32_t nS, int32_t b, uint32_t theta, uint64_t seed,
+                 int32_t mode, int32_t *blockers, int32_t *n_blockers, int32_t *calls_out,
+                 uint64_t *stats, int model)
 {
     if (theta == 0 || b < 0 || !blockers || !n_blockers) return ORC_EINVAL;
     if (mode != ORC_AG && mode != ORC_GR) return ORC_EINVAL;
@@ -539,7 +647,7 @@ int orc_greedy(int32_t n, const int32_t *row_ptr, const int32_t *col, const floa
     uint64_t tot[4] = {0, 0, 0, 0}, one[4];
     uint64_t call = 0;
     int32_t nb = 0;
-    int rc = state_init(&st, n, row_ptr, col, prob, S, nS);
+    int rc = state_init(&st, n, row_ptr, col, prob, S, nS, model);
     if (rc) return rc;
     uint8_t *blk = (uint8_t *)calloc((size_t)n, 1);
     uint64_t *D = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
@@ -619,4 +727,13 @@ done:
     free(blk); free(D); free(cand); free(B); free(snap);
     state_free(&st);
     return rc;
+}
+
+int orc_greedy(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
+               const int32_t *S, int32_t nS, int32_t b, uint32_t theta, uint64_t seed,
+               int32_t mode, int32_t *blockers, int32_t *n_blockers, int32_t *calls_out,
+               uint64_t *stats)
+{
+    return orc_greedy_m(n, row_ptr, col, prob, S, nS, b, theta, seed, mode, blockers,
+                        n_blockers, calls_out, stats, ORC_IC);
 }

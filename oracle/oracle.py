@@ -16,6 +16,7 @@ _SRC = os.path.join(_HERE, "imin_oracle.c")
 _LIB = os.path.join(_HERE, "libimin_oracle.so")
 
 AG, GR = 0, 1
+IC, LT = 0, 1  # propagation models: independent cascade; linear threshold (triggering)
 
 _lib = None
 
@@ -46,12 +47,21 @@ def _load():
     lib.orc_sample.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int32, P, ctypes.c_uint64,
                                ctypes.c_uint32, P, P]
     lib.orc_sample.restype = ctypes.c_int64
+    lib.orc_sample_m.argtypes = lib.orc_sample.argtypes + [ctypes.c_int]
+    lib.orc_sample_m.restype = ctypes.c_int64
+    lib.orc_lt_trigger.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_uint64, ctypes.c_uint32,
+                                   ctypes.c_int32]
+    lib.orc_lt_trigger.restype = ctypes.c_int64
     lib.orc_decrease.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int32, P, ctypes.c_uint32,
                                  ctypes.c_uint64, P, P]
     lib.orc_decrease.restype = ctypes.c_int
+    lib.orc_decrease_m.argtypes = lib.orc_decrease.argtypes + [ctypes.c_int]
+    lib.orc_decrease_m.restype = ctypes.c_int
     lib.orc_greedy.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, P, P, P, P]
     lib.orc_greedy.restype = ctypes.c_int
+    lib.orc_greedy_m.argtypes = lib.orc_greedy.argtypes + [ctypes.c_int]
+    lib.orc_greedy_m.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -88,7 +98,16 @@ def edge_live(key: int, j: int, e: int, p: float) -> bool:
     return bool(_load().orc_edge_live(key, j, e, float(p)))
 
 
-def sample(n, row_ptr, col, prob, seeds, blocked, key: int, j: int):
+def lt_trigger(n, row_ptr, col, w, key: int, j: int, u: int) -> int:
+    """LT: the in-edge id u chooses in sample j (its triggering set), or -1."""
+    row_ptr, col, w = _graph(row_ptr, col, w)
+    r = _load().orc_lt_trigger(n, _ptr(row_ptr), _ptr(col), _ptr(w), key, j, u)
+    if r < -1:
+        raise OracleError(f"orc_lt_trigger failed: {r}")
+    return int(r)
+
+
+def sample(n, row_ptr, col, prob, seeds, blocked, key: int, j: int, model: int = IC):
     """One sampled graph: (reached count, c[n], idom[n]); see orc_sample."""
     lib = _load()
     row_ptr, col, prob = _graph(row_ptr, col, prob)
@@ -96,14 +115,14 @@ def sample(n, row_ptr, col, prob, seeds, blocked, key: int, j: int):
     blk = None if blocked is None else np.ascontiguousarray(blocked, dtype=np.uint8)
     c = np.zeros(n, dtype=np.int32)
     idom = np.zeros(n, dtype=np.int32)
-    r = lib.orc_sample(n, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(S), S.shape[0], _ptr(blk),
-                       key, j, _ptr(c), _ptr(idom))
+    r = lib.orc_sample_m(n, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(S), S.shape[0],
+                         _ptr(blk), key, j, _ptr(c), _ptr(idom), model)
     if r < 0:
         raise OracleError(f"orc_sample failed: {r}")
     return int(r), c, idom
 
 
-def decrease(n, row_ptr, col, prob, seeds, blocked, theta: int, key: int):
+def decrease(n, row_ptr, col, prob, seeds, blocked, theta: int, key: int, model: int = IC):
     """Integer decrease counts D[n] and stats (samples, reached, edges scanned, live edges)."""
     lib = _load()
     row_ptr, col, prob = _graph(row_ptr, col, prob)
@@ -111,15 +130,16 @@ def decrease(n, row_ptr, col, prob, seeds, blocked, theta: int, key: int):
     blk = None if blocked is None else np.ascontiguousarray(blocked, dtype=np.uint8)
     D = np.zeros(n, dtype=np.uint64)
     st = np.zeros(4, dtype=np.uint64)
-    rc = lib.orc_decrease(n, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(S), S.shape[0], _ptr(blk),
-                          theta, key, _ptr(D), _ptr(st))
+    rc = lib.orc_decrease_m(n, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(S), S.shape[0],
+                            _ptr(blk), theta, key, _ptr(D), _ptr(st), model)
     if rc != 0:
         raise OracleError(f"orc_decrease failed: {rc}")
     return D, dict(samples=int(st[0]), reached=int(st[1]), edges_scanned=int(st[2]),
                    live_edges=int(st[3]))
 
 
-def greedy(n, row_ptr, col, prob, seeds, b: int, theta: int, seed: int, mode: int):
+def greedy(n, row_ptr, col, prob, seeds, b: int, theta: int, seed: int, mode: int,
+           model: int = IC):
     """Blocker slots in order, number of decrease calls, summed stats."""
     lib = _load()
     row_ptr, col, prob = _graph(row_ptr, col, prob)
@@ -128,8 +148,8 @@ def greedy(n, row_ptr, col, prob, seeds, b: int, theta: int, seed: int, mode: in
     nb = np.zeros(1, dtype=np.int32)
     calls = np.zeros(1, dtype=np.int32)
     st = np.zeros(4, dtype=np.uint64)
-    rc = lib.orc_greedy(n, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(S), S.shape[0], b, theta,
-                        seed, mode, _ptr(out), _ptr(nb), _ptr(calls), _ptr(st))
+    rc = lib.orc_greedy_m(n, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(S), S.shape[0], b,
+                          theta, seed, mode, _ptr(out), _ptr(nb), _ptr(calls), _ptr(st), model)
     if rc != 0:
         raise OracleError(f"orc_greedy failed: {rc}")
     return out[: nb[0]].copy(), int(calls[0]), dict(samples=int(st[0]), reached=int(st[1]),
