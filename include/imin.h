@@ -53,6 +53,12 @@ enum {
     IMIN_ERANGE = -4   /* a size exceeds what the library supports (e.g. m >= 2^31) */
 };
 
+/* Propagation models for imin_graph_create_model. */
+enum {
+    IMIN_IC = 0, /* independent cascade (Section III-A) */
+    IMIN_LT = 1  /* linear threshold, the triggering-model extension (Section V-E) */
+};
+
 /* Greedy drivers for imin_greedy. */
 enum {
     IMIN_AG = 0, /* AdvancedGreedy, Algorithm 3 */
@@ -94,6 +100,22 @@ typedef struct {
  */
 IMIN_API int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col,
                       const float *prob, imin_graph **out);
+
+/*
+ * imin_graph_create_model -- as imin_graph_create, under a chosen propagation model.
+ *   IMIN_IC  prob[e] is the propagation probability of edge e (imin_graph_create).
+ *   IMIN_LT  prob[e] is the weight w(v,u) of edge e = (v,u); the weights of u's in-edges
+ *            must sum to at most 1 (up to 1e-5 of rounding; IMIN_EINVAL otherwise). In a
+ *            sampled graph u keeps at most one in-edge, each with probability its weight
+ *            (u's triggering set, Section V-E): with its in-edges e_1 < e_2 < ... (by edge
+ *            id) and bound_k = min(2^24, ceil(2^24 * (w_1 + ... + w_k))) from fp64 running
+ *            sums, u keeps e_k in sample j iff bound_{k-1} <= R < bound_k, where R = word
+ *            (u & 3) of Philox4x32-10 at counter (u >> 2, j, 1, 0) and the call's key,
+ *            shifted right by 8. Every call and greedy driver then works as under IC.
+ */
+IMIN_API int imin_graph_create_model(int32_t n, int32_t m, const int32_t *row_ptr,
+                                     const int32_t *col, const float *prob, int model,
+                                     imin_graph **out);
 
 /* Release a handle and all device memory it owns. NULL is ignored. */
 IMIN_API void imin_graph_destroy(imin_graph *g);
@@ -216,8 +238,9 @@ typedef struct {
  *   count   >= 1; the total of theta over the batch must not exceed 2^31 (IMIN_ERANGE).
  *   launch  the wave kernel's launch shape (NULL: defaults); the graphs' own imin_set_small
  *           settings do not apply here.
- * Errors: IMIN_EINVAL (any instance invalid as for imin_greedy, a graph repeated, NULL
- * inst, negative launch values), IMIN_ERANGE, IMIN_ENOMEM, IMIN_EDEVICE.
+ * Errors: IMIN_EINVAL (any instance invalid as for imin_greedy, a graph repeated, graphs of
+ * different models, NULL inst, negative launch values), IMIN_ERANGE, IMIN_ENOMEM,
+ * IMIN_EDEVICE.
  */
 IMIN_API int imin_greedy_batch(imin_instance *inst, int32_t count, int mode,
                                const imin_launch *launch);

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libimin.so")
 
 IMIN_OK, IMIN_EINVAL, IMIN_ENOMEM, IMIN_EDEVICE, IMIN_ERANGE = 0, -1, -2, -3, -4
 IMIN_AG, IMIN_GR = 0, 1
+IMIN_IC, IMIN_LT = 0, 1
 
 
 class IminError(RuntimeError):
@@ -81,6 +82,9 @@ def load() -> ctypes.CDLL:
     lib.imin_graph_create.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P,
                                       ctypes.POINTER(ctypes.c_void_p)]
     lib.imin_graph_create.restype = ctypes.c_int
+    lib.imin_graph_create_model.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_void_p)]
+    lib.imin_graph_create_model.restype = ctypes.c_int
     lib.imin_graph_destroy.argtypes = [P]
     lib.imin_graph_destroy.restype = None
     lib.imin_decrease.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_uint32, ctypes.c_uint64, P,
@@ -132,14 +136,14 @@ def imin_strerror(status: int) -> str:
     return load().imin_strerror(status).decode()
 
 
-def imin_graph_create(n: int, row_ptr, col, prob) -> int:
+def imin_graph_create(n: int, row_ptr, col, prob, model: int = IMIN_IC) -> int:
     """Returns the opaque handle (an integer address)."""
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
     col = np.ascontiguousarray(col, dtype=np.int32)
     prob = np.ascontiguousarray(prob, dtype=np.float32)
     h = ctypes.c_void_p()
-    rc = load().imin_graph_create(int(n), int(col.shape[0]), _p(row_ptr), _p(col), _p(prob),
-                                  ctypes.byref(h))
+    rc = load().imin_graph_create_model(int(n), int(col.shape[0]), _p(row_ptr), _p(col),
+                                        _p(prob), int(model), ctypes.byref(h))
     if rc != IMIN_OK:
         raise IminError("imin_graph_create", rc)
     return h.value
@@ -238,10 +242,11 @@ def imin_greedy_batch(problems, mode: int = IMIN_AG, launch=None):
 class Graph:
     """A device-resident graph (one ``imin_graph`` handle)."""
 
-    def __init__(self, row_ptr, col, prob):
+    def __init__(self, row_ptr, col, prob, model: int = IMIN_IC):
         row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
         self.n = int(row_ptr.shape[0] - 1)
-        self.handle = imin_graph_create(self.n, row_ptr, col, prob)
+        self.model = int(model)
+        self.handle = imin_graph_create(self.n, row_ptr, col, prob, model)
 
     def decrease(self, seeds, blocked=None, theta: int = 1000, seed: int = 0):
         return imin_decrease(self.handle, self.n, seeds, blocked, theta, seed)

@@ -234,6 +234,7 @@ void describe(imin_graph *g, int32_t nseeds, uint64_t seed, uint32_t theta)
     I.row_ptr = g->d_row_ptr;
     I.col4 = g->d_col4;
     I.thr4 = g->d_thr4;
+    I.lo4 = g->d_lo4;
     I.in_ptr = g->d_in_ptr;
     I.in_edge = g->d_in_edge;
     I.inelig = g->d_inelig;
@@ -342,6 +343,8 @@ int launch_large_on(imin_graph *g, const LargeTarget &t, uint32_t theta, uint64_
     a.row_ptr = g->d_row_ptr;
     a.col4 = g->d_col4;
     a.thr4 = t.thr4;
+    a.lo4 = g->d_lo4;
+    a.lt = g->model == IMIN_LT ? 1 : 0;
     a.seeds = t.seeds;
     a.nseeds = t.nseeds;
     a.n = g->n;
@@ -434,7 +437,7 @@ int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uin
 
 int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst, uint32_t total,
                 uint32_t round, const imin_launch &shape, int num_cus, bool select,
-                int32_t slot, hipStream_t stream)
+                int32_t slot, bool lt, hipStream_t stream)
 {
     if (total > ms.cap) return IMIN_ERANGE;
     int rc = guard_epochs(ms.main_ws, total, stream);
@@ -456,6 +459,7 @@ int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst,
     s.total = total;
     s.round = round;
     small_shape(s, shape);
+    s.lt = lt ? 1 : 0;
     s.next = ms.ctrl + 0;
     s.spill_inst = ms.si;
     s.spill_j = ms.sj;
@@ -479,6 +483,7 @@ int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst,
     a.sample_inst = ms.si;
     a.ovf_inst = ms.oi;
     a.round = round;
+    a.lt = lt ? 1 : 0;
     if (!ok(imin::launch_decrease(a, stream))) return IMIN_EDEVICE;
     if (spill) {
         a.sample_list = ms.oj;
@@ -536,6 +541,7 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed,
         s.round = call;
         small_shape(s, g->small_launch);
         s.reach_only = reach_only ? 1 : 0;
+        s.lt = g->model == IMIN_LT ? 1 : 0;
         s.next = g->d_sctrl + 0;
         s.spill_inst = nullptr;
         s.spill_j = g->d_sj;
@@ -620,6 +626,7 @@ void destroy(imin_graph *g)
     dfree(g->d_col4);
     dfree(g->d_thr4);
     dfree(g->d_thr_orig);
+    dfree(g->d_lo4);
     dfree(g->d_in_ptr);
     dfree(g->d_in_edge);
     dfree(g->d_inelig);
@@ -702,7 +709,14 @@ const char *imin_strerror(int status)
 int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col,
                       const float *prob, imin_graph **out)
 {
+    return imin_graph_create_model(n, m, row_ptr, col, prob, IMIN_IC, out);
+}
+
+int imin_graph_create_model(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col,
+                            const float *prob, int model, imin_graph **out)
+{
     if (!out || !row_ptr || n <= 0 || m < 0) return IMIN_EINVAL;
+    if (model != IMIN_IC && model != IMIN_LT) return IMIN_EINVAL;
     if (n == INT32_MAX) return IMIN_ERANGE;
     if (row_ptr[0] != 0 || row_ptr[n] != m) return IMIN_EINVAL;
     for (int32_t v = 0; v < n; ++v)
@@ -749,7 +763,7 @@ int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
         hcol[(size_t)e] = (uint32_t)col[e];
         hthr[(size_t)e] = live_threshold(prob[e]);
     }
-    // in-edge index: edge ids grouped by target (counting sort)
+    // in-edge index: edge ids grouped by target, ascending (counting sort)
     std::vector<int32_t> in_ptr, in_edge;
     try {
         in_ptr.assign((size_t)n + 1, 0);
@@ -764,6 +778,35 @@ int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
         std::vector<int32_t> fill(in_ptr.begin(), in_ptr.end() - 1);
         for (int32_t e = 0; e < m; ++e) in_edge[(size_t)fill[(size_t)col[e]]++] = e;
     }
+    // Linear-threshold model: the in-edges of v split [0, 2^24) into consecutive intervals,
+    // edge k of v (ascending id) getting [bound_{k-1}, bound_k) with
+    // bound_k = min(2^24, ceil(2^24 * (w_1 + ... + w_k))) from fp64 running sums.
+    std::vector<uint32_t> hlo;
+    if (model == IMIN_LT) {
+        try {
+            hlo.assign(hthr.size(), 0u);
+        } catch (...) {
+            delete g;
+            return IMIN_ENOMEM;
+        }
+        for (int32_t v = 0; v < n; ++v) {
+            double sum = 0.0;
+            uint32_t prev = 0;
+            for (int32_t k = in_ptr[(size_t)v]; k < in_ptr[(size_t)v + 1]; ++k) {
+                const int32_t e = in_edge[(size_t)k];
+                sum += (double)prob[e];
+                const double bound = std::min(16777216.0, std::ceil(sum * 16777216.0));
+                hlo[(size_t)e] = prev;
+                hthr[(size_t)e] = (uint32_t)bound;
+                prev = (uint32_t)bound;
+            }
+            if (sum > 1.0 + 1e-5) {
+                delete g;
+                return IMIN_EINVAL;
+            }
+        }
+    }
+    g->model = model;
     g->words = (n + 31) / 32;
     bool good =
         ok(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking)) &&
@@ -785,7 +828,8 @@ int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
         ok(hipMalloc(&g->d_inst, sizeof(imin::InstanceDesc))) &&
         ok(hipMalloc(&g->d_part_d, (size_t)g->parts * sizeof(unsigned long long))) &&
         ok(hipMalloc(&g->d_part_i, (size_t)g->parts * sizeof(int32_t))) &&
-        ok(hipMalloc(&g->d_x, sizeof(int32_t)));
+        ok(hipMalloc(&g->d_x, sizeof(int32_t))) &&
+        (model != IMIN_LT || ok(hipMalloc(&g->d_lo4, hlo.size() * sizeof(uint32_t))));
     if (!good) {
         (void)hipGetLastError();
         destroy(g);
@@ -802,7 +846,9 @@ int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
         !ok(hipMemcpy(g->d_in_ptr, in_ptr.data(), in_ptr.size() * sizeof(int32_t),
                       hipMemcpyHostToDevice)) ||
         !ok(hipMemcpy(g->d_in_edge, in_edge.data(), in_edge.size() * sizeof(int32_t),
-                      hipMemcpyHostToDevice))) {
+                      hipMemcpyHostToDevice)) ||
+        (model == IMIN_LT && !ok(hipMemcpy(g->d_lo4, hlo.data(), hlo.size() * sizeof(uint32_t),
+                                           hipMemcpyHostToDevice)))) {
         destroy(g);
         return IMIN_EDEVICE;
     }
@@ -1052,7 +1098,8 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         imin_instance &in = inst[i];
         if (!in.g || in.theta == 0 || in.b < 0 || !in.n_blockers || (in.b > 0 && !in.blockers))
             return IMIN_EINVAL;
-        if (in.g->device != inst[0].g->device) return IMIN_EINVAL;
+        if (in.g->device != inst[0].g->device || in.g->model != inst[0].g->model)
+            return IMIN_EINVAL;
         BatchItem &it = items[(size_t)i];
         it.in = &in;
         it.g = in.g;
@@ -1149,7 +1196,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         if (rc) return rc;
         if (!ok(hipEventRecord(k0, bs))) return IMIN_EDEVICE;
         rc = multi_round(ms.s, d_table.p, active, prefix[(size_t)active], (uint32_t)r, shape,
-                         g0->num_cus, true, r, bs);
+                         g0->num_cus, true, r, g0->model == IMIN_LT, bs);
         if (rc) return rc;
         if (!ok(hipEventRecord(k1, bs))) return IMIN_EDEVICE;
     }

@@ -5,7 +5,9 @@
 //   1. decides live edges on the fly: edge e is live iff (W >> 8) < thr[e], W = word e&3 of
 //      Philox4x32-10(counter (e>>2, j, 0, 0), key) -- nothing about the sample is stored
 //      (Definition 4, live-edge sampling). One Philox call serves the 4 edges of a 32-byte
-//      edge quad, and a lane works on one quad at a time;
+//      edge quad, and a lane works on one quad at a time. Under the linear-threshold model
+//      (Section V-E) edge e = (v, u) is live iff u's choice falls in e's interval
+//      [lo[e], thr[e]) (philox.h);
 //   2. runs a level-synchronous BFS from the merged seed (Section V, multiple seeds to one
 //      seed) over live edges. An edge into a seed or a blocked vertex (Definition 2) has
 //      threshold 0 in the call's threshold array, so it is never live.
@@ -64,6 +66,7 @@ struct Call {
     const int32_t *row_ptr;
     const uint4 *col4;
     const uint4 *thr4;
+    const uint4 *lo4;
     const int32_t *seeds;
     int32_t nseeds;
     uint32_t key_lo, key_hi;
@@ -155,6 +158,7 @@ __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView
 // the edge quads of a chunk are spread evenly over the workgroup, two independent quads in
 // flight per thread. A quad's thresholds are always read; its targets only when one of its
 // coins comes up live.
+template <bool kLT>
 __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv, Shared &sh,
                        bool from_seeds, int lo, int hi, uint32_t j, uint32_t epoch,
                        uint32_t &scanned, uint32_t &live)
@@ -196,11 +200,24 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
             locate(sh, cnt, has2 ? q2 : q, l2, quad2);
             const uint4 t1 = c.thr4[quad1];
             const uint4 t2 = c.thr4[quad2];
-            const uint32_t m1 = live_mask(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], t1);
-            const uint32_t m2 = has2 ? live_mask(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], t2) : 0u;
+            uint32_t m1, m2;
             uint4 c1 = make_uint4(0, 0, 0, 0), c2 = make_uint4(0, 0, 0, 0);
-            if (m1) c1 = c.col4[quad1];
-            if (m2) c2 = c.col4[quad2];
+            if (kLT) {
+                // a vertex-keyed choice per edge: the targets are needed first
+                const uint4 b1 = c.lo4[quad1];
+                const uint4 b2 = c.lo4[quad2];
+                c1 = c.col4[quad1];
+                c2 = c.col4[quad2];
+                m1 = live_mask_lt(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], b1, t1, c1);
+                m2 = has2 ? live_mask_lt(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], b2,
+                                         t2, c2)
+                          : 0u;
+            } else {
+                m1 = live_mask(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], t1);
+                m2 = has2 ? live_mask(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], t2) : 0u;
+                if (m1) c1 = c.col4[quad1];
+                if (m2) c2 = c.col4[quad2];
+            }
             visit_mask(a, sv, sh, m1, c1, from_seeds ? 0 : base + l1, epoch, live);
             visit_mask(a, sv, sh, m2, c2, from_seeds ? 0 : base + l2, epoch, live);
         }
@@ -225,7 +242,7 @@ __device__ __forceinline__ void wave_add(unsigned *dst, uint32_t v)
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
 }
 
-template <bool kMulti>
+template <bool kMulti, bool kLT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void decrease_kernel(DecreaseArgs a)
 {
@@ -248,15 +265,16 @@ void decrease_kernel(DecreaseArgs a)
         const uint32_t j = a.sample_list ? a.sample_list[idx] : idx;
         // This sample's problem: the launch's own, or an instance of a many-instance launch
         // (all instances' vertex ids fit the slot maps).
-        Call c{a.row_ptr, a.col4, a.thr4, a.seeds, a.nseeds, a.key_lo, a.key_hi, a.D, a.stats};
+        Call c{a.row_ptr, a.col4, a.thr4, a.lo4, a.seeds, a.nseeds, a.key_lo, a.key_hi, a.D,
+               a.stats};
         uint32_t inst_i = 0;
         if (kMulti) {
             inst_i = __builtin_amdgcn_readfirstlane(a.sample_inst[idx]);
             const InstanceDesc &I = a.inst[inst_i];
             const unsigned long long key =
                 (((unsigned long long)I.seed_hi << 32) | I.seed_lo) + a.round;
-            c = Call{I.row_ptr, I.col4, I.thr4,        I.seeds, I.nseeds,
-                     (uint32_t)key, (uint32_t)(key >> 32), I.D, I.stats};
+            c = Call{I.row_ptr, I.col4,  I.thr4,        I.lo4, I.seeds, I.nseeds,
+                     (uint32_t)key, (uint32_t)(key >> 32), I.D,     I.stats};
         }
         ++epoch;
         if (tid == 0) {
@@ -277,14 +295,14 @@ void decrease_kernel(DecreaseArgs a)
         __syncthreads();
 
         uint32_t p_scanned = 0, p_live = 0;
-        expand(a, c, sv, sh, true, 0, c.nseeds, j, epoch, p_scanned, p_live);
+        expand<kLT>(a, c, sv, sh, true, 0, c.nseeds, j, epoch, p_scanned, p_live);
         int L = 1, lo = 1;
         int hi = sh.tail;
         __syncthreads();
         while (lo < hi) {
             if (sh.ovf) break;
             if (tid == 0) sv.lvl[L + 1] = hi;
-            expand(a, c, sv, sh, false, lo, hi, j, epoch, p_scanned, p_live);
+            expand<kLT>(a, c, sv, sh, false, lo, hi, j, epoch, p_scanned, p_live);
             lo = hi;
             hi = sh.tail;
             ++L;
@@ -383,10 +401,15 @@ void decrease_kernel(DecreaseArgs a)
 hipError_t launch_decrease(const DecreaseArgs &a, hipStream_t stream)
 {
     if (a.ws.slots <= 0) return hipErrorInvalidValue;
-    if (a.inst)
-        hipLaunchKernelGGL(decrease_kernel<true>, dim3(a.ws.slots), dim3(kBlock), 0, stream, a);
+    const dim3 grid(a.ws.slots), block(kBlock);
+    if (a.inst && a.lt)
+        hipLaunchKernelGGL((decrease_kernel<true, true>), grid, block, 0, stream, a);
+    else if (a.inst)
+        hipLaunchKernelGGL((decrease_kernel<true, false>), grid, block, 0, stream, a);
+    else if (a.lt)
+        hipLaunchKernelGGL((decrease_kernel<false, true>), grid, block, 0, stream, a);
     else
-        hipLaunchKernelGGL(decrease_kernel<false>, dim3(a.ws.slots), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL((decrease_kernel<false, false>), grid, block, 0, stream, a);
     return hipGetLastError();
 }
 

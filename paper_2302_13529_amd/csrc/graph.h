@@ -19,6 +19,8 @@ struct imin_graph {
     uint4 *d_thr4 = nullptr;      // working live thresholds, same layout: 0 on every edge into
                                   // a vertex of `masked`
     uint4 *d_thr_orig = nullptr;  // the thresholds ceil(p * 2^24) as created
+    int model = 0;                // IMIN_IC or IMIN_LT
+    uint4 *d_lo4 = nullptr;       // linear-threshold model: interval lower bounds
     int32_t *d_in_ptr = nullptr;  // in-edges of v: d_in_edge[d_in_ptr[v] .. d_in_ptr[v+1])
     int32_t *d_in_edge = nullptr; // edge ids, grouped by target
     hipStream_t stream = nullptr;
@@ -128,7 +130,7 @@ void multi_free(MultiScratch &ms);
 // Nothing waits for the host. D is cleared first.
 int multi_round(MultiScratch &ms, const InstanceDesc *inst, int32_t ninst, uint32_t total,
                 uint32_t round, const imin_launch &shape, int num_cus, bool select,
-                int32_t slot, hipStream_t stream);
+                int32_t slot, bool lt, hipStream_t stream);
 // The error words of the last rounds (0 when every sample was counted).
 int multi_errors(MultiScratch &ms, uint32_t *wave_err, uint32_t *wg_err, hipStream_t stream);
 

@@ -55,6 +55,8 @@ struct DecreaseArgs {
     const uint4 *col4;       // ceil(m / 4) quads of edge targets (4 edges = 16 bytes)
     const uint4 *thr4;       // ceil(m / 4) quads of live thresholds ceil(p * 2^24), 0 for
                              // edges into seeds and blocked vertices
+    const uint4 *lo4;        // linear-threshold model: interval lower bounds (thr4 = upper)
+    int32_t lt;              // 1: linear-threshold model, 0: independent cascade
     const int32_t *seeds;    // distinct seeds
     int32_t nseeds;
     int32_t n;
@@ -96,6 +98,7 @@ struct InstanceDesc {
     const int32_t *row_ptr;
     const uint4 *col4;
     uint4 *thr4;              // working thresholds (the batched argmax masks its winners)
+    const uint4 *lo4;         // linear-threshold model: interval lower bounds
     const int32_t *in_ptr;    // in-edges of v: in_edge[in_ptr[v] .. in_ptr[v+1])
     const int32_t *in_edge;   // edge ids
     uint32_t *inelig;         // bit v set: v is a seed or blocked (the argmax adds winners)
@@ -121,6 +124,7 @@ struct SmallArgs {
     uint32_t round;           // added to every instance's seed to form the key
     int32_t quad_limit;       // a frontier chunk with more edge quads goes to the large kernel
     int32_t pick_div;         // runs of samples: about remaining / (pick_div * waves)
+    int32_t lt;               // every instance uses the linear-threshold model
     int32_t reach_only;       // count reached vertices only (spread estimates)
     uint32_t *next;           // work counter
     uint32_t *spill_inst;     // samples left to the large kernel: instance, sample index

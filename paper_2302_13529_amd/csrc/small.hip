@@ -5,7 +5,8 @@
 // instances of the launch, so many graphs (the batched form) or one graph share the same
 // launch. Per sample:
 //   * live edges are decided per 4-edge quad with the same Philox4x32-10 coin as the large
-//     kernel (Definition 4); lanes work on consecutive quads of the frontier;
+//     kernel (Definition 4; or the linear-threshold model's vertex choices, Section V-E);
+//     lanes work on consecutive quads of the frontier;
 //   * reachability from the merged seed is a wave-synchronous BFS. The live edges a wave
 //     finds are claimed one at a time in lane order: the ids of the reached vertices are
 //     mirrored in registers (4 per lane), so "already reached?" is one compare and a ballot;
@@ -277,6 +278,7 @@ __device__ __forceinline__ void expand_seeds_cached(const SeedCache &sc, WaveSta
 }
 
 // Expand frontier [lo, hi): seeds of the instance (source = merged seed 0) or local ids.
+template <bool kLT>
 __device__ void expand_small(const InstanceDesc &I, WaveState &ws, Mirror &m, SampleCtx &cx,
                              bool from_seeds, int lo, int hi, uint32_t j, uint32_t key_lo,
                              uint32_t key_hi, int quad_limit)
@@ -321,7 +323,12 @@ __device__ void expand_small(const InstanceDesc &I, WaveState &ws, Mirror &m, Sa
                 // both loads in flight at once: one memory round trip per level
                 const uint4 thr = I.thr4[quad];
                 col = I.col4[quad];
-                mask = live_mask(quad, j, key_lo, key_hi, ws.e0[l], ws.e1[l], thr);
+                if (kLT) {
+                    const uint4 lo4 = I.lo4[quad];
+                    mask = live_mask_lt(quad, j, key_lo, key_hi, ws.e0[l], ws.e1[l], lo4, thr, col);
+                } else {
+                    mask = live_mask(quad, j, key_lo, key_hi, ws.e0[l], ws.e1[l], thr);
+                }
                 src = from_seeds ? 0 : base + l;
             }
             cx.live += (uint32_t)__builtin_popcount(mask);
@@ -367,6 +374,7 @@ __device__ __forceinline__ void flush(const InstanceDesc &I, Tally &t)
 
 // One sample: BFS, dominators, subtree sizes into D. Returns false when it must be handed
 // to the large kernel.
+template <bool kLT>
 __device__ bool run_sample(const SmallArgs &a, const InstanceDesc &I, const SeedCache &sc,
                            WaveState &ws, uint32_t j, Tally &tally)
 {
@@ -393,15 +401,15 @@ __device__ bool run_sample(const SmallArgs &a, const InstanceDesc &I, const Seed
         ws.lvl[1] = 1;
     }
     wave_sync();
-    if (sc.total >= 0)
+    if (!kLT && sc.total >= 0)
         expand_seeds_cached(sc, ws, m, cx, j, key_lo, key_hi);
     else
-        expand_small(I, ws, m, cx, true, 0, I.nseeds, j, key_lo, key_hi, a.quad_limit);
+        expand_small<kLT>(I, ws, m, cx, true, 0, I.nseeds, j, key_lo, key_hi, a.quad_limit);
     int flo = 1, fhi = cx.nV;
     while (!cx.ovf && flo < fhi) {
         if (lane == 0) ws.lvl[cx.L + 1] = fhi;
         wave_sync();
-        expand_small(I, ws, m, cx, false, flo, fhi, j, key_lo, key_hi, a.quad_limit);
+        expand_small<kLT>(I, ws, m, cx, false, flo, fhi, j, key_lo, key_hi, a.quad_limit);
         flo = fhi;
         fhi = cx.nV;
         ++cx.L;
@@ -466,6 +474,7 @@ __device__ bool run_sample(const SmallArgs &a, const InstanceDesc &I, const Seed
     return true;
 }
 
+template <bool kLT>
 __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a)
 {
     __shared__ SmallShared smem;
@@ -509,10 +518,11 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
                 I = a.inst[cur];
                 cur_lo = I.sample_base;
                 cur_hi = I.sample_base + I.theta;
-                build_seed_cache(I, ws, sc);
+                if (kLT) sc.total = -1;  // vertex-keyed choices: no per-quad seed cache
+                else build_seed_cache(I, ws, sc);
             }
             const uint32_t j = idx - cur_lo;
-            if (!run_sample(a, I, sc, ws, j, tally) && lane == 0) {
+            if (!run_sample<kLT>(a, I, sc, ws, j, tally) && lane == 0) {
                 const uint32_t pos = atomicAdd(a.spill_count, 1u);
                 if (a.spill_inst) a.spill_inst[pos] = (uint32_t)cur;
                 a.spill_j[pos] = j;
@@ -527,7 +537,11 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
 hipError_t launch_decrease_small(const SmallArgs &a, int grid, hipStream_t stream)
 {
     if (grid <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(decrease_small_kernel, dim3(grid), dim3(kSmallBlock), 0, stream, a);
+    if (a.lt)
+        hipLaunchKernelGGL(decrease_small_kernel<true>, dim3(grid), dim3(kSmallBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL(decrease_small_kernel<false>, dim3(grid), dim3(kSmallBlock), 0, stream,
+                           a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,125 @@
+"""Linear-threshold (triggering-model) sampling on the GPU against the checker, bit-exact.
+
+Weighted-cascade weights 1/indeg(v) sum to one over every vertex's in-edges, so the same
+synthetic graphs serve as LT inputs (Section V-E).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2302_13529_amd import graphgen as gg
+from tests import helpers as H
+from tests.test_oracle_lt import _random_lt_graph
+
+pytestmark = pytest.mark.gpu
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def check(g, n, rp, c, w, seeds, blocked, theta, key, label):
+    case(f"{label}: LT decrease theta={theta} key={key}")
+    D, st = g.decrease(seeds, blocked, theta, key)
+    Do, so = orc.decrease(n, rp, c, w, seeds, blocked, theta, key, model=orc.LT)
+    assert np.array_equal(D, Do), f"{label}: D differs at {np.nonzero(D != Do)[0][:10]}"
+    for k in ("samples", "reached", "edges_scanned", "live_edges"):
+        assert st[k] == so[k], (label, k, st[k], so[k])
+    assert st["live_edges"] == st["reached"]  # one live in-edge per reached vertex
+    return D, st
+
+
+def test_tiny_lt_all_paths(gpu):
+    t = gg.tiny_plain()
+    g = gpu.Graph(t.row_ptr, t.col, t.prob, model=gpu.IMIN_LT)
+    rng = np.random.default_rng(2)
+    blocked = np.zeros(t.n, np.uint8)
+    blocked[[v for v in rng.choice(t.n, 50, replace=False) if v not in t.seeds]] = 1
+    for enable in (-1, 0, 1):
+        g.set_small(enable)
+        for blk in (None, blocked):
+            check(g, t.n, t.row_ptr, t.col, t.prob, t.seeds, blk, 700, 11, f"tiny/{enable}")
+    g.set_small(1, dict(quad_limit=1))
+    check(g, t.n, t.row_ptr, t.col, t.prob, t.seeds, None, 300, 2, "tiny/handover")
+    g.set_small(0)
+    g.set_launch(3, 1)
+    check(g, t.n, t.row_ptr, t.col, t.prob, t.seeds, None, 300, 2, "tiny/spill")
+    g.close()
+
+
+def test_random_lt_graphs(gpu):
+    rng = np.random.default_rng(13)
+    for k in range(12):
+        n = int(rng.integers(3, 60))
+        rp, c, w = _random_lt_graph(rng, n, int(rng.integers(n, 4 * n)))
+        seeds = list(map(int, rng.choice(n, size=int(rng.integers(1, 4)), replace=False)))
+        g = gpu.Graph(rp, c, w, model=gpu.IMIN_LT)
+        check(g, n, rp, c, w, seeds, None, 500, k, f"rand{k}")
+        g.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["AG", "GR"])
+def test_lt_greedy(gpu, mode):
+    t = gg.tiny_plain()
+    g = gpu.Graph(t.row_ptr, t.col, t.prob, model=gpu.IMIN_LT)
+    case(f"tiny LT greedy mode={mode}")
+    B, st = g.greedy(t.seeds, 6, 500, 4, mode)
+    Bo, calls, so = orc.greedy(t.n, t.row_ptr, t.col, t.prob, t.seeds, 6, 500, 4, mode,
+                               model=orc.LT)
+    assert list(B) == list(Bo) and st["reached"] == so["reached"]
+    g.close()
+
+
+def test_lt_rmat17(gpu):
+    t = gg.rmat_plain()
+    g = gpu.Graph(t.row_ptr, t.col, t.prob, model=gpu.IMIN_LT)
+    check(g, t.n, t.row_ptr, t.col, t.prob, t.seeds, None, 60, 5, "rmat17")
+    g.close()
+
+
+def test_lt_batch_and_server(gpu):
+    insts = gg.batched_instances(count=6, seed=9)
+    # TR probabilities (at most 0.1 each) are not LT weights; use 1/indeg instead
+    graphs, ws = [], []
+    for t in insts:
+        indeg = np.bincount(t.col, minlength=t.n)
+        w = (1.0 / np.maximum(indeg[t.col], 1)).astype(np.float32)
+        ws.append(w)
+        graphs.append(gpu.Graph(t.row_ptr, t.col, w, model=gpu.IMIN_LT))
+    probs = [(g.handle, t.seeds, 3, 300, t.seed) for g, t in zip(graphs, insts)]
+    case("LT batch of 6")
+    res = gpu.imin_greedy_batch(probs)
+    for (B, st), g, t, w in zip(res, graphs, insts, ws):
+        Bp, sp = g.greedy(t.seeds, 3, 300, t.seed, gpu.IMIN_AG)
+        assert list(B) == list(Bp) and st["reached"] == sp["reached"]
+    Bo, _, so = orc.greedy(insts[0].n, insts[0].row_ptr, insts[0].col, ws[0], insts[0].seeds, 3,
+                           300, insts[0].seed, 0, model=orc.LT)
+    assert list(res[0][0]) == list(Bo)
+    case("LT server")
+    srv = gpu.Server(graphs[1], max_active=3, max_theta=400)
+    tks = [srv.submit(insts[1].seeds[:k + 1], 2, 100 * (k + 1), k) for k in range(4)]
+    while srv.step() != (0, 0):
+        pass
+    for k, tk in enumerate(tks):
+        B, st = srv.result(tk, 2)
+        Bp, sp = graphs[1].greedy(insts[1].seeds[:k + 1], 2, 100 * (k + 1), k, gpu.IMIN_AG)
+        assert list(B) == list(Bp) and st["reached"] == sp["reached"]
+    srv.close()
+    # a batch may not mix models
+    ic = gpu.Graph(insts[0].row_ptr, insts[0].col, insts[0].prob)
+    with pytest.raises(gpu.IminError) as e:
+        gpu.imin_greedy_batch([(ic.handle, insts[0].seeds, 1, 10, 0), probs[1]])
+    assert e.value.status == gpu.IMIN_EINVAL
+    ic.close()
+    for g in graphs:
+        g.close()
+
+
+def test_lt_weights_validated(gpu):
+    rp, c, w = H.csr_from_edges(3, [(0, 2, 0.75), (1, 2, 0.5)])
+    with pytest.raises(gpu.IminError) as e:
+        gpu.Graph(rp, c, w, model=gpu.IMIN_LT)
+    assert e.value.status == gpu.IMIN_EINVAL
+    with pytest.raises(gpu.IminError):
+        gpu.Graph(rp, c, w, model=7)
+    gpu.Graph(rp, c, w).close()  # fine under IC
