@@ -58,11 +58,11 @@ def traffic_from_profile(path: str, kernel_source: str):
         return None
 
 
-def cpu_baseline(inst, theta_sample: int) -> dict:
+def cpu_baseline(inst, theta_sample: int, model: str = "ic") -> dict:
     from oracle import oracle as orc
     t0 = time.perf_counter()
     _, st = orc.decrease(inst.n, inst.row_ptr, inst.col, inst.prob, inst.seeds, None,
-                         theta_sample, 0)
+                         theta_sample, 0, model=orc.LT if model == "lt" else orc.IC)
     dt = time.perf_counter() - t0
     return {"value": st["samples"] / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
             "sample": f"{theta_sample} of the {inst.theta} samples of greedy round 0 "
@@ -242,6 +242,8 @@ def main() -> int:
     ap.add_argument("--cpu-samples", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", choices=["rmat22", "batched", "served"], default="rmat22")
+    ap.add_argument("--model", choices=["ic", "lt"], default="ic",
+                    help="rmat22: propagation model (lt: WC weights as linear-threshold weights)")
     ap.add_argument("--queries", type=int, default=2000, help="served: queries of the mix")
     ap.add_argument("--plain-queries", type=int, default=40,
                     help="served: queries timed one plain call at a time")
@@ -271,7 +273,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     print("[bench] generating rmat22 workload", file=sys.stderr, flush=True)
     inst = gg.large_plain()
-    g = binding.Graph(inst.row_ptr, inst.col, inst.prob)
+    model = binding.IMIN_LT if args.model == "lt" else binding.IMIN_IC
+    g = binding.Graph(inst.row_ptr, inst.col, inst.prob, model=model)
     theta = inst.theta
     print(f"[bench] warmup {args.warmup} rounds", file=sys.stderr, flush=True)
     if args.warmup > 0:
@@ -305,7 +308,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": inst.name, "n": inst.n, "m": inst.m, "seeds": len(inst.seeds),
+        "config": {"workload": inst.name + ("_lt" if args.model == "lt" else ""),
+                   "model": args.model.upper(), "n": inst.n, "m": inst.m, "seeds": len(inst.seeds),
                    "theta": theta, "step": "one AdvancedGreedy round", "parallelism": "none"},
         "teps": st["edges_scanned"] / dt,
         "reached_per_sample": st["reached"] / samples,
@@ -318,7 +322,7 @@ def main() -> int:
     }
     if not args.no_cpu:
         print(f"[bench] cpu baseline on {args.cpu_samples} samples", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_samples)
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_samples, args.model)
     print(json.dumps(out), flush=True)
     return 0
 

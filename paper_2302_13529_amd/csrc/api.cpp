@@ -550,6 +550,22 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed,
         if (!ok(imin::launch_decrease_small(s, small_grid(g->num_cus, g->small_launch),
                                             g->stream)))
             return IMIN_EDEVICE;
+        if (g->small_mode == -1 && g->auto_pending) {
+            // Automatic policy, first round of the call: when the wave kernel handed over
+            // most samples, the workgroup kernel gets its full slot count now, and the wave
+            // kernel sits out the call's later rounds (results are the same either way).
+            g->auto_pending = false;
+            uint32_t handed = 0;
+            if (!ok(hipMemcpyAsync(&handed, g->d_sctrl + 1, sizeof(handed),
+                                   hipMemcpyDeviceToHost, g->stream)) ||
+                !ok(hipStreamSynchronize(g->stream)))
+                return IMIN_EDEVICE;
+            if ((double)handed > (1.0 - kSmallKeepShare) * (double)theta) {
+                g->small_auto_off = true;
+                rc = size_workspaces(g, 0);
+                if (rc) return rc;
+            }
+        }
         rc = launch_large(g, nseeds, theta, seed + call, g->d_sj, g->d_sctrl + 1, reach_only);
     } else {
         rc = launch_large(g, nseeds, theta, seed + call, nullptr, nullptr, reach_only);
@@ -590,27 +606,12 @@ int finish_call(imin_graph *g, imin_stats *stats)
     return IMIN_OK;
 }
 
-// Automatic wave-kernel policy: after a call's first round with the wave kernel on, keep it
-// for the call's later rounds only if it finished most of the samples (the results are the
-// same either way).
-int auto_check(imin_graph *g)
-{
-    if (g->small_mode != -1 || g->small_auto_off) return IMIN_OK;
-    unsigned long long st[kStats];
-    if (!ok(hipMemcpyAsync(st, g->d_stats, sizeof(st), hipMemcpyDeviceToHost, g->stream)) ||
-        !ok(hipStreamSynchronize(g->stream)))
-        return IMIN_EDEVICE;
-    if ((double)st[5] >= kSmallKeepShare * (double)st[0]) return IMIN_OK;
-    g->small_auto_off = true;
-    // the workgroup kernel now takes every sample: give it the full slot count
-    return size_workspaces(g, 0);
-}
-
 int begin_call(imin_graph *g)
 {
     if (!ok(hipSetDevice(g->device))) return IMIN_EDEVICE;
     g->kev_used = 0;
     g->small_auto_off = false;  // every call tries the wave kernel in its first round
+    g->auto_pending = true;
     if (!ok(hipEventRecord(g->ev0, g->stream))) return IMIN_EDEVICE;
     return IMIN_OK;
 }
@@ -976,10 +977,6 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
         for (int32_t r = 0; r < rounds; ++r) {
             rc = decrease_round(g, ns, theta, seed, call);
             if (rc) return rc;
-            if (call == 0) {
-                rc = auto_check(g);
-                if (rc) return rc;
-            }
             ++call;
             if (!ok(imin::launch_argmax_apply(g->d_D, g->d_inelig, 0, g->n, g->d_part_d,
                                               g->d_part_i, g->parts, g->d_inelig, nullptr,
@@ -1013,10 +1010,6 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
         for (int32_t r = 0; r < k; ++r) {
             rc = decrease_round(g, ns, theta, seed, call);
             if (rc) return rc;
-            if (call == 0) {
-                rc = auto_check(g);
-                if (rc) return rc;
-            }
             ++call;
             if (!ok(imin::launch_argmax_apply(g->d_D, g->d_cand, 1, g->n, g->d_part_d,
                                               g->d_part_i, g->parts, g->d_inelig, g->d_cand,
@@ -1046,10 +1039,6 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
                 return IMIN_EDEVICE;
             rc = decrease_round(g, ns, theta, seed, call);
             if (rc) return rc;
-            if (call == 0) {
-                rc = auto_check(g);
-                if (rc) return rc;
-            }
             ++call;
             if (!ok(imin::launch_argmax_apply(g->d_D, g->d_inelig, 0, g->n, g->d_part_d,
                                               g->d_part_i, g->parts, g->d_inelig, nullptr,

@@ -8,7 +8,7 @@
 namespace imin {
 namespace {
 
-constexpr int kSelBlock = 256;
+constexpr int kSelBlock = 1024;
 
 __global__ void fill_u64_kernel(unsigned long long *p, int64_t count, unsigned long long value)
 {
@@ -142,14 +142,29 @@ __global__ void batch_zero_kernel(const InstanceDesc *inst)
         I.D[v] = 0ull;
 }
 
-// One workgroup per instance.
+// One workgroup per instance; each thread takes 4 vertices at a time so that several loads
+// are in flight.
 __global__ void batch_argmax_kernel(const InstanceDesc *inst, int32_t slot)
 {
     const InstanceDesc &I = inst[blockIdx.x];
     unsigned long long bd = 0;
     int bi = -1;
-    for (int32_t v = threadIdx.x; v < I.n; v += kSelBlock)
-        if (!((I.inelig[v >> 5] >> (v & 31)) & 1u)) better(bd, bi, I.D[v], (int)v);
+    constexpr int kStep = 4 * kSelBlock;
+    for (int32_t base = 4 * (int32_t)threadIdx.x; base < I.n; base += kStep) {
+        unsigned long long d[4];
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int32_t v = base + k;
+            d[k] = v < I.n ? I.D[v] : 0ull;
+            w[k] = v < I.n ? I.inelig[v >> 5] : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int32_t v = base + k;
+            if (v < I.n && !((w[k] >> (v & 31)) & 1u)) better(bd, bi, d[k], (int)v);
+        }
+    }
     block_best(bd, bi);
     if (threadIdx.x == 0) {
         if (bi >= 0) {
