@@ -139,6 +139,9 @@ typedef struct {
     int model;             /* ORC_IC or ORC_LT */
     const float *w;        /* LT: edge weights */
     int32_t *in_ptr, *in_edge; /* LT: in-edges of each vertex, ascending edge id */
+    int64_t *trig;         /* LT: the choice of each vertex in the current sample ... */
+    uint64_t *trig_tag;    /* ... valid when its tag equals the sample's tag */
+    uint64_t tag;
     uint32_t *thr;         /* per edge */
     uint8_t *is_seed;      /* per vertex */
     const uint8_t *blocked;/* per vertex, may be NULL */
@@ -159,10 +162,17 @@ typedef struct {
     uint64_t edges_scanned, live_edges;
 } orc_state;
 
-static int live_in_sample(const orc_state *st, uint64_t key, uint32_t j, int64_t e)
+static int live_in_sample(orc_state *st, uint64_t key, uint32_t j, int64_t e)
 {
-    if (st->model == ORC_LT)
-        return lt_trigger(st->in_ptr, st->in_edge, st->w, key, j, st->col[e]) == e;
+    if (st->model == ORC_LT) {
+        /* each vertex's choice is drawn once per sample and remembered for the sample */
+        int32_t u = st->col[e];
+        if (st->trig_tag[u] != st->tag) {
+            st->trig[u] = lt_trigger(st->in_ptr, st->in_edge, st->w, key, j, u);
+            st->trig_tag[u] = st->tag;
+        }
+        return st->trig[u] == e;
+    }
     return edge_live(key, j, e, st->thr[e]);
 }
 
@@ -212,6 +222,7 @@ static int32_t visit(orc_state *st, int32_t v)
  */
 static int build_sample(orc_state *st, uint64_t key, uint32_t j)
 {
+    st->tag++;  /* a new sample: forget the remembered choices */
     st->nloc = 0;
     st->nedge = 0;
     st->glob[0] = -1;
@@ -378,6 +389,7 @@ static void subtree_sizes(orc_state *st)
 static void state_free(orc_state *st)
 {
     free(st->thr); free(st->is_seed); free(st->seeds); free(st->in_ptr); free(st->in_edge);
+    free(st->trig); free(st->trig_tag);
     free(st->loc); free(st->glob); free(st->esrc); free(st->edst);
     free(st->succ_ptr); free(st->succ); free(st->pred_ptr); free(st->pred);
     free(st->num); free(st->vert); free(st->parent); free(st->semi); free(st->idom);
@@ -465,6 +477,11 @@ static int state_init(orc_state *st, int32_t n, const int32_t *row_ptr, const in
     if (model == ORC_LT) {
         rc = build_in_edges(st, m);
         if (!rc) rc = check_lt_weights(st);
+        if (!rc) {
+            st->trig = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+            st->trig_tag = (uint64_t *)calloc((size_t)n, sizeof(uint64_t));
+            if (!st->trig || !st->trig_tag) rc = ORC_ENOMEM;
+        }
         if (rc) { state_free(st); return rc; }
     }
     for (int32_t i = 0; i < nS; ++i) st->is_seed[S[i]] = 1;
