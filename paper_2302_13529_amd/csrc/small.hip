@@ -110,7 +110,7 @@ __device__ __forceinline__ int mirror_find(const Mirror &m, int c)
         if (m.g[r] == c) hit = r * 64 + lane_id();
     const unsigned long long b = __ballot(hit >= 0);
     if (!b) return -1;
-    return __shfl(hit, (int)__builtin_ctzll(b), 64);
+    return __builtin_amdgcn_readlane(hit, (int)__builtin_ctzll(b));
 }
 
 struct SampleCtx {
@@ -158,8 +158,9 @@ __device__ __forceinline__ void claim_all(WaveState &ws, Mirror &m, SampleCtx &c
         if (!pend || cx.ovf) break;
         const int leader = (int)__builtin_ctzll(pend);
         const int myc = mask ? pick(col, __builtin_ctz(mask)) : 0;
-        const int c = __builtin_amdgcn_readfirstlane(__shfl(myc, leader, 64));
-        const int s = __builtin_amdgcn_readfirstlane(__shfl(src, leader, 64));
+        // direct reads of the leader's registers (no LDS round trip)
+        const int c = __builtin_amdgcn_readlane(myc, leader);
+        const int s = __builtin_amdgcn_readlane(src, leader);
         if (lane == leader) mask &= mask - 1;
         claim(ws, m, cx, c, s);
     }
