@@ -86,7 +86,8 @@ def bench_batched(args) -> dict:
         print("[bench] launch shape from the autotuner", file=sys.stderr, flush=True)
         tuned_key, tuned = autotune.tuned_batch_launch(insts, probs, tune_if_missing=args.tune)
         if tuned:
-            launch = tuned
+            launch = dict(tuned)
+    launch["graph"] = 1 if args.graph else 0
     print(f"[bench] warmup: plain and batched, {args.warmup} each", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         for g, t in zip(graphs, insts):
@@ -254,6 +255,8 @@ def main() -> int:
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--quad-limit", type=int, default=0)
     ap.add_argument("--pick-div", type=int, default=0)
+    ap.add_argument("--graph", action="store_true",
+                    help="batched workload: capture each call's rounds into one HIP graph")
     ap.add_argument("--tune", action="store_true",
                     help="batched workload: tune the launch shape if no cached entry exists")
     args = ap.parse_args()

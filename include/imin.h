@@ -190,11 +190,14 @@ IMIN_API int imin_set_launch(imin_graph *g, int32_t slots, int64_t extra_cap);
  *                 rows fit the kernel's 128-quad seed cache.
  *   pick_div      waves take runs of consecutive samples of about a 1/pick_div share of
  *                 what remains per wave, between 4 and 64 samples (default 4).
+ *   graph         imin_greedy_batch only: 1 captures all rounds of the call into one HIP
+ *                 graph (kernel nodes only) and launches it once; 0 launches them directly.
  */
 typedef struct {
     int32_t waves_per_cu;
     int32_t quad_limit;
     int32_t pick_div;
+    int32_t graph;
 } imin_launch;
 
 /*

@@ -193,7 +193,8 @@ void small_shape(imin::SmallArgs &s, const imin_launch &l)
 
 bool launch_ok(const imin_launch *l)
 {
-    return !l || (l->waves_per_cu >= 0 && l->quad_limit >= 0 && l->pick_div >= 0);
+    return !l || (l->waves_per_cu >= 0 && l->quad_limit >= 0 && l->pick_div >= 0 &&
+                  (l->graph == 0 || l->graph == 1));
 }
 
 int ensure_B(imin_graph *g, int32_t b)
@@ -437,15 +438,17 @@ int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uin
 
 int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst, uint32_t total,
                 uint32_t round, const imin_launch &shape, int num_cus, bool select,
-                int32_t slot, bool lt, hipStream_t stream)
+                int32_t slot, bool lt, hipStream_t stream, bool guarded)
 {
     if (total > ms.cap) return IMIN_ERANGE;
-    int rc = guard_epochs(ms.main_ws, total, stream);
-    if (rc) return rc;
     const bool spill = ms.big_ws.slots > 0;
-    if (spill) {
-        rc = guard_epochs(ms.big_ws, total, stream);
+    if (!guarded) {
+        int rc = guard_epochs(ms.main_ws, total, stream);
         if (rc) return rc;
+        if (spill) {
+            rc = guard_epochs(ms.big_ws, total, stream);
+            if (rc) return rc;
+        }
     }
     // words 0, 1, 3, 4, 5 restart every round; the error words 2 and 6 accumulate
     if (!ok(imin::launch_batch_zero(inst, ninst, stream)) ||
@@ -680,6 +683,35 @@ struct BatchItem {
     std::vector<int32_t> seeds;
     std::vector<uint32_t> inelig;
     int32_t rounds = 0;
+};
+
+// A stream capture that is always ended, and the graph it made, released at scope exit.
+struct GraphCapture {
+    hipStream_t stream = nullptr;  // non-null while capturing
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int finish()
+    {
+        hipStream_t s = stream;
+        stream = nullptr;
+        if (!ok(hipStreamEndCapture(s, &graph)) ||
+            !ok(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0))) {
+            (void)hipGetLastError();
+            return IMIN_EDEVICE;
+        }
+        return IMIN_OK;
+    }
+    ~GraphCapture()
+    {
+        if (stream) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
 };
 
 // Frees a many-instance scratch when the call ends, however it ends.
@@ -1177,17 +1209,50 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         !ok(imin::launch_batch_setup(d_table.p, d_stages.p, d_stage.p, count, bs)))
         return IMIN_EDEVICE;
     // Rounds: every launch is queued at once; nothing waits for the host until the end.
-    int32_t active = count;
-    for (int32_t r = 0; r < max_rounds; ++r) {
-        while (active > 0 && items[(size_t)active - 1].rounds <= r) --active;
+    const bool lt = g0->model == IMIN_LT;
+    if (shape.graph) {
+        // One HIP graph of kernel nodes for all rounds. The epochs the rounds will use are
+        // reserved first, so no clearing (a memset) can fall inside the capture.
+        uint64_t all = 0;
+        for (int32_t r = 0, act = count; r < max_rounds; ++r) {
+            while (act > 0 && items[(size_t)act - 1].rounds <= r) --act;
+            all += prefix[(size_t)act];
+        }
+        if (all >= 0xFFFFFFFEull) return IMIN_ERANGE;
+        rc = guard_epochs(ms.s.main_ws, (uint32_t)all, bs);
+        if (!rc && ms.s.big_ws.slots > 0) rc = guard_epochs(ms.s.big_ws, (uint32_t)all, bs);
+        if (rc) return rc;
+        GraphCapture cap;
+        if (!ok(hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal))) return IMIN_EDEVICE;
+        cap.stream = bs;
+        int32_t act = count;
+        for (int32_t r = 0; r < max_rounds; ++r) {
+            while (act > 0 && items[(size_t)act - 1].rounds <= r) --act;
+            rc = multi_round(ms.s, d_table.p, act, prefix[(size_t)act], (uint32_t)r, shape,
+                             g0->num_cus, true, r, lt, bs, true);
+            if (rc) return rc;
+        }
+        rc = cap.finish();
+        if (rc) return rc;
         hipEvent_t k0, k1;
         rc = kernel_events(g0, &k0, &k1);
         if (rc) return rc;
-        if (!ok(hipEventRecord(k0, bs))) return IMIN_EDEVICE;
-        rc = multi_round(ms.s, d_table.p, active, prefix[(size_t)active], (uint32_t)r, shape,
-                         g0->num_cus, true, r, g0->model == IMIN_LT, bs);
-        if (rc) return rc;
-        if (!ok(hipEventRecord(k1, bs))) return IMIN_EDEVICE;
+        if (!ok(hipEventRecord(k0, bs)) || !ok(hipGraphLaunch(cap.exec, bs)) ||
+            !ok(hipEventRecord(k1, bs)) || !ok(hipStreamSynchronize(bs)))
+            return IMIN_EDEVICE;
+    } else {
+        int32_t active = count;
+        for (int32_t r = 0; r < max_rounds; ++r) {
+            while (active > 0 && items[(size_t)active - 1].rounds <= r) --active;
+            hipEvent_t k0, k1;
+            rc = kernel_events(g0, &k0, &k1);
+            if (rc) return rc;
+            if (!ok(hipEventRecord(k0, bs))) return IMIN_EDEVICE;
+            rc = multi_round(ms.s, d_table.p, active, prefix[(size_t)active], (uint32_t)r,
+                             shape, g0->num_cus, true, r, lt, bs, false);
+            if (rc) return rc;
+            if (!ok(hipEventRecord(k1, bs))) return IMIN_EDEVICE;
+        }
     }
     // Results: every graph's blocker slots, counters and error flag, gathered into one
     // buffer, then one copy and one wait.

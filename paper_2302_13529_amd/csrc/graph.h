@@ -129,9 +129,10 @@ void multi_free(MultiScratch &ms);
 // [0, total), keys seed + round): the wave kernel, the workgroup kernels for the samples it
 // hands over, then (select) the AdvancedGreedy choice of each instance written to B[slot].
 // Nothing waits for the host. D is cleared first.
+// guarded: the caller has reserved the epochs of this round (no clearing may be issued).
 int multi_round(MultiScratch &ms, const InstanceDesc *inst, int32_t ninst, uint32_t total,
                 uint32_t round, const imin_launch &shape, int num_cus, bool select,
-                int32_t slot, bool lt, hipStream_t stream);
+                int32_t slot, bool lt, hipStream_t stream, bool guarded);
 // The error words of the last rounds (0 when every sample was counted).
 int multi_errors(MultiScratch &ms, uint32_t *wave_err, uint32_t *wg_err, hipStream_t stream);
 

@@ -92,5 +92,5 @@ def test_batch_rejects_null_graph_before_touching_a_device():
     arr[0].theta = 10
     assert lib.imin_greedy_batch(arr, 1, 0, None) == binding.IMIN_EINVAL
     assert lib.imin_greedy_batch(arr, 0, 0, None) == binding.IMIN_EINVAL
-    bad = binding.imin_launch(-1, 0, 0)
-    assert lib.imin_greedy_batch(arr, 1, 0, ctypes.byref(bad)) == binding.IMIN_EINVAL
+    for bad in (binding.imin_launch(-1, 0, 0, 0), binding.imin_launch(0, 0, 0, 2)):
+        assert lib.imin_greedy_batch(arr, 1, 0, ctypes.byref(bad)) == binding.IMIN_EINVAL

@@ -106,13 +106,15 @@ def test_batch_equals_plain_and_oracle(gpu, batch16):
         assert st["live_edges"] == so["live_edges"], i
         Bp, sp = g.greedy(t.seeds, b, th, t.seed, gpu.IMIN_AG)
         assert list(Bp) == list(B), i
-    for wpc, ql, pd in ((4, 0, 0), (8, 1, 1), (32, 64, 16)):
-        case(f"batched AG, waves_per_cu={wpc} quad_limit={ql} pick_div={pd}")
+    for wpc, ql, pd, gr in ((4, 0, 0, 0), (8, 1, 1, 0), (32, 64, 16, 0), (0, 0, 0, 1),
+                            (8, 1, 2, 1), (0, 0, 0, 1)):
+        case(f"batched AG, waves_per_cu={wpc} quad_limit={ql} pick_div={pd} graph={gr}")
         res2 = gpu.imin_greedy_batch(probs, gpu.IMIN_AG,
-                                     dict(waves_per_cu=wpc, quad_limit=ql, pick_div=pd))
+                                     dict(waves_per_cu=wpc, quad_limit=ql, pick_div=pd, graph=gr))
         for (B, st), (B2, st2) in zip(res, res2):
             assert list(B) == list(B2)
             assert st["reached"] == st2["reached"] and st["live_edges"] == st2["live_edges"]
+            assert st["samples"] == st2["samples"]
         if ql == 1:  # most seed frontiers are handed over at once
             assert sum(st2["wave_samples"] for _, st2 in res2) < \
                 sum(st2["samples"] for _, st2 in res2)
