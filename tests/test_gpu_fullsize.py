@@ -61,3 +61,23 @@ def test_served_graph_full_size(gpu):
         assert st["edges_scanned"] == so["edges_scanned"]
     srv.close()
     g.close()
+
+
+def test_rmat17_full_theta_round(gpu):
+    """C2 at full size: one Algorithm 2 call with theta = 10^4 on the 131k-vertex R-MAT graph,
+    every count against the checker (about a minute of checker time)."""
+    t = gg.rmat_plain()
+    g = gpu.Graph(t.row_ptr, t.col, t.prob)
+    case("rmat17 decrease, theta 10^4")
+    D, st = g.decrease(t.seeds, None, t.theta, 0)
+    Do, so = orc.decrease(t.n, t.row_ptr, t.col, t.prob, t.seeds, None, t.theta, 0)
+    assert np.array_equal(D, Do)
+    for k in ("samples", "reached", "edges_scanned", "live_edges"):
+        assert st[k] == so[k], k
+    # the first greedy round blocks the argmax of these counts (ties to the smaller id)
+    B, _ = g.greedy(t.seeds, 1, t.theta, 0, gpu.IMIN_AG)
+    cand = np.ones(t.n, bool)
+    cand[t.seeds] = False
+    best = int(np.flatnonzero(cand)[np.argmax(Do[cand])])
+    assert int(B[0]) == best
+    g.close()
