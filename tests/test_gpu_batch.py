@@ -198,3 +198,31 @@ def test_autotuned_launch_gives_identical_results(gpu, batch16, tmp_path, monkey
     assert launch is None or isinstance(launch, dict)
     for g in graphs:
         g.close()
+
+
+def test_batch_degenerate_instances(gpu):
+    """Instances with nothing to do, one sample, one vertex, or no edges, mixed with normal
+    ones; every result equals the plain call."""
+    rp0, c0, p0 = H.csr_from_edges(1, [])                        # one vertex, the seed
+    rp1, c1, p1 = H.csr_from_edges(5, [])                        # no edges
+    rp2, c2, p2 = H.csr_from_edges(4, [(0, 1, 1.0), (1, 2, 1.0), (2, 3, 1.0)])
+    t = gg.tiny_plain()
+    graphs = [gpu.Graph(rp0, c0, p0), gpu.Graph(rp1, c1, p1), gpu.Graph(rp2, c2, p2),
+              gpu.Graph(rp2, c2, p2), gpu.Graph(t.row_ptr, t.col, t.prob)]
+    probs = [(graphs[0].handle, [0], 3, 10, 0),      # no candidate: zero rounds
+             (graphs[1].handle, [2], 2, 1, 5),       # one sample, nothing reachable
+             (graphs[2].handle, [0, 1, 2, 3], 2, 7, 1),  # every vertex a seed
+             (graphs[3].handle, [0], 0, 7, 1),       # b = 0
+             (graphs[4].handle, t.seeds, 3, 1, 9)]   # theta = 1
+    case("batch of degenerate instances")
+    res = gpu.imin_greedy_batch(probs)
+    for g, (h, S, b, th, sd), (B, st) in zip(graphs, probs, res):
+        Bp, sp = g.greedy(S, b, th, sd, gpu.IMIN_AG)
+        assert list(B) == list(Bp) and st["samples"] == sp["samples"]
+        assert st["reached"] == sp["reached"]
+    assert [len(B) for B, _ in res] == [0, 2, 0, 0, 3]
+    case("a batch of one")
+    (B, st), = gpu.imin_greedy_batch([probs[4]])
+    assert list(B) == list(res[4][0])
+    for g in graphs:
+        g.close()

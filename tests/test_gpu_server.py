@@ -135,3 +135,22 @@ def test_server_errors(gpu):
         srv.result(tk, 3)  # taken already
     srv.close()
     g.close()
+
+
+def test_server_degenerate_queries(gpu):
+    t = gg.tiny_plain()
+    g = gpu.Graph(t.row_ptr, t.col, t.prob)
+    srv = gpu.Server(g, max_active=4, max_theta=100)
+    qs = [dict(seeds=[3], b=0, theta=10, seed=0),                 # nothing to do
+          dict(seeds=list(range(t.n)), b=5, theta=10, seed=1),    # every vertex a seed
+          dict(seeds=[7, 7, 7], b=2, theta=1, seed=2),            # duplicate seeds, one sample
+          dict(seeds=[11], b=3, theta=100, seed=3)]
+    case("server: degenerate queries")
+    res, _, _, _ = serve.run(srv, qs)
+    for q, (B, st) in zip(qs, res):
+        Bp, sp = g.greedy(q["seeds"], q["b"], q["theta"], q["seed"], gpu.IMIN_AG)
+        assert list(B) == list(Bp) and st["reached"] == sp["reached"]
+        assert st["samples"] == sp["samples"]
+    assert len(res[0][0]) == 0 and len(res[1][0]) == 0
+    srv.close()
+    g.close()
