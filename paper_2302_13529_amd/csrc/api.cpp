@@ -50,7 +50,7 @@ void free_ws(Workspace &ws)
 
 size_t slot_bytes(int64_t n, int64_t lcap, int64_t xcap)
 {
-    return (size_t)n * sizeof(imin::SlotEntry) + (size_t)lcap * sizeof(imin::LocalVtx) +
+    return (size_t)n * sizeof(uint32_t) + (size_t)lcap * sizeof(imin::LocalVtx) +
            (size_t)(lcap + 1) * sizeof(int32_t) + (size_t)xcap * sizeof(int2) + sizeof(uint32_t);
 }
 
@@ -59,8 +59,12 @@ int alloc_ws(Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap
 {
     if (ws.slots == slots && ws.n == n && ws.lcap == lcap && ws.xcap == xcap) return IMIN_OK;
     free_ws(ws);
+    // the map's local-id field holds lid + 1 <= lcap, and leaves at least one epoch bit
+    int32_t lbits = 1;
+    while (lbits < 32 && (int64_t(1) << lbits) <= lcap) ++lbits;
+    if (lbits > 31) return IMIN_ERANGE;
     const size_t S = (size_t)slots;
-    bool good = ok(hipMalloc(&ws.map, S * (size_t)n * sizeof(imin::SlotEntry))) &&
+    bool good = ok(hipMalloc(&ws.map, S * (size_t)n * sizeof(uint32_t))) &&
                 ok(hipMalloc(&ws.loc, S * (size_t)lcap * sizeof(imin::LocalVtx))) &&
                 ok(hipMalloc(&ws.lvl, S * (size_t)(lcap + 1) * sizeof(int32_t))) &&
                 ok(hipMalloc(&ws.extra, S * (size_t)std::max<int64_t>(xcap, 1) * sizeof(int2))) &&
@@ -70,7 +74,7 @@ int alloc_ws(Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap
         (void)hipGetLastError();
         return IMIN_ENOMEM;
     }
-    if (!ok(hipMemsetAsync(ws.map, 0, S * (size_t)n * sizeof(imin::SlotEntry), stream)) ||
+    if (!ok(hipMemsetAsync(ws.map, 0, S * (size_t)n * sizeof(uint32_t), stream)) ||
         !ok(hipMemsetAsync(ws.epoch, 0, S * sizeof(uint32_t), stream))) {
         free_ws(ws);
         return IMIN_EDEVICE;
@@ -79,7 +83,7 @@ int alloc_ws(Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap
     ws.n = n;
     ws.lcap = lcap;
     ws.xcap = xcap;
-    ws.epochs_used = 0;
+    ws.lbits = lbits;
     ws.bytes = S * slot_bytes(n, lcap, xcap);
     return IMIN_OK;
 }
@@ -104,7 +108,7 @@ int size_workspaces(imin_graph *g, int32_t max_slots)
         free_b += g->main_ws.bytes;  // the current allocation is released before a new one
         const size_t per = slot_bytes(g->n, lcap, xcap);
         const size_t by_mem = std::max<size_t>(1, (free_b / 2) / per);
-        slots = (int32_t)std::min<size_t>((size_t)2 * g->num_cus, by_mem);
+        slots = (int32_t)std::min<size_t>((size_t)imin::kSlotsPerCu * g->num_cus, by_mem);
         if (max_slots > 0) slots = std::min(slots, max_slots);
         // keep a working allocation that is at least as large, or a full-size one that the
         // free memory now sizes slightly differently
@@ -127,23 +131,6 @@ int size_workspaces(imin_graph *g, int32_t max_slots)
 int prepare_workspaces(imin_graph *g)
 {
     return size_workspaces(g, small_enabled(g) ? kSmallModeSlots : 0);
-}
-
-// Keep every slot's 32-bit epoch from wrapping: a launch of theta samples raises any slot's
-// epoch by at most theta.
-int guard_epochs(Workspace &ws, uint32_t theta, hipStream_t stream)
-{
-    if (ws.slots == 0) return IMIN_OK;
-    if (ws.epochs_used + theta + 1 < 0xFFFFFFFFull) {
-        ws.epochs_used += theta;
-        return IMIN_OK;
-    }
-    if (!ok(hipMemsetAsync(ws.map, 0, (size_t)ws.slots * ws.n * sizeof(imin::SlotEntry),
-                           stream)) ||
-        !ok(hipMemsetAsync(ws.epoch, 0, (size_t)ws.slots * sizeof(uint32_t), stream)))
-        return IMIN_EDEVICE;
-    ws.epochs_used = theta;
-    return IMIN_OK;
 }
 
 int ensure_ovf(imin_graph *g, uint32_t theta)
@@ -331,13 +318,7 @@ int kernel_events(imin_graph *g, hipEvent_t *a, hipEvent_t *b)
 int launch_large_on(imin_graph *g, const LargeTarget &t, uint32_t theta, uint64_t key,
                     const uint32_t *list, const uint32_t *count, bool reach_only)
 {
-    int rc = guard_epochs(*t.main_ws, theta, g->stream);
-    if (rc) return rc;
     const bool spill = t.big_ws->slots > 0;
-    if (spill) {
-        rc = guard_epochs(*t.big_ws, theta, g->stream);
-        if (rc) return rc;
-    }
     if (!ok(imin::launch_fill_u32(t.ctrl, 3, 0, g->stream))) return IMIN_EDEVICE;
     DecreaseArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -395,14 +376,14 @@ int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uin
     const int64_t lcap = max_n + 1;
     const int64_t xmax = max_m + 1;
     const int64_t xcap = std::min<int64_t>(std::max<int64_t>(4096, lcap / 4), xmax);
-    // two workgroup slots per compute unit, as single calls use, within a quarter of the
+    // kSlotsPerCu workgroup slots per compute unit, as single calls use, within a quarter of the
     // free memory
     size_t free_b = 0, total_b = 0;
     if (!ok(hipMemGetInfo(&free_b, &total_b))) return IMIN_EDEVICE;
     free_b += ms.main_ws.bytes;
     const size_t per = slot_bytes(max_n, lcap, xcap);
     const int32_t slots = (int32_t)std::max<size_t>(
-        1, std::min<size_t>((size_t)2 * std::max(1, num_cus), (free_b / 4) / per));
+        1, std::min<size_t>((size_t)imin::kSlotsPerCu * std::max(1, num_cus), (free_b / 4) / per));
     int rc = alloc_ws(ms.main_ws, max_n, slots, lcap, xcap, stream);
     if (rc) return rc;
     if (xcap < xmax) {
@@ -438,18 +419,10 @@ int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uin
 
 int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst, uint32_t total,
                 uint32_t round, const imin_launch &shape, int num_cus, bool select,
-                int32_t slot, bool lt, hipStream_t stream, bool guarded)
+                int32_t slot, bool lt, hipStream_t stream)
 {
     if (total > ms.cap) return IMIN_ERANGE;
     const bool spill = ms.big_ws.slots > 0;
-    if (!guarded) {
-        int rc = guard_epochs(ms.main_ws, total, stream);
-        if (rc) return rc;
-        if (spill) {
-            rc = guard_epochs(ms.big_ws, total, stream);
-            if (rc) return rc;
-        }
-    }
     // words 0, 1, 3, 4, 5 restart every round; the error words 2 and 6 accumulate
     if (!ok(imin::launch_batch_zero(inst, ninst, stream)) ||
         !ok(imin::launch_fill_u32(ms.ctrl, 2, 0, stream)) ||
@@ -1211,17 +1184,8 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
     // Rounds: every launch is queued at once; nothing waits for the host until the end.
     const bool lt = g0->model == IMIN_LT;
     if (shape.graph) {
-        // One HIP graph of kernel nodes for all rounds. The epochs the rounds will use are
-        // reserved first, so no clearing (a memset) can fall inside the capture.
-        uint64_t all = 0;
-        for (int32_t r = 0, act = count; r < max_rounds; ++r) {
-            while (act > 0 && items[(size_t)act - 1].rounds <= r) --act;
-            all += prefix[(size_t)act];
-        }
-        if (all >= 0xFFFFFFFEull) return IMIN_ERANGE;
-        rc = guard_epochs(ms.s.main_ws, (uint32_t)all, bs);
-        if (!rc && ms.s.big_ws.slots > 0) rc = guard_epochs(ms.s.big_ws, (uint32_t)all, bs);
-        if (rc) return rc;
+        // One HIP graph of kernel nodes for all rounds (slots clear their own maps when
+        // their epochs wrap, so no memset is ever needed inside).
         GraphCapture cap;
         if (!ok(hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal))) return IMIN_EDEVICE;
         cap.stream = bs;
@@ -1229,7 +1193,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         for (int32_t r = 0; r < max_rounds; ++r) {
             while (act > 0 && items[(size_t)act - 1].rounds <= r) --act;
             rc = multi_round(ms.s, d_table.p, act, prefix[(size_t)act], (uint32_t)r, shape,
-                             g0->num_cus, true, r, lt, bs, true);
+                             g0->num_cus, true, r, lt, bs);
             if (rc) return rc;
         }
         rc = cap.finish();
@@ -1249,7 +1213,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
             if (rc) return rc;
             if (!ok(hipEventRecord(k0, bs))) return IMIN_EDEVICE;
             rc = multi_round(ms.s, d_table.p, active, prefix[(size_t)active], (uint32_t)r,
-                             shape, g0->num_cus, true, r, lt, bs, false);
+                             shape, g0->num_cus, true, r, lt, bs);
             if (rc) return rc;
             if (!ok(hipEventRecord(k1, bs))) return IMIN_EDEVICE;
         }

@@ -75,7 +75,7 @@ struct Call {
 };
 
 struct SlotView {
-    SlotEntry *map;
+    uint32_t *map;
     LocalVtx *loc;
     int32_t *lvl;
     int2 *extra;
@@ -101,16 +101,19 @@ struct Shared {
 
 // Live edge src -> w: w is claimed for this sample if it was not yet reached, or the edge is
 // kept as an extra edge (edges from the merged seed never matter for dominators: their
-// targets are its children).
+// targets are its children). tag = this sample's epoch << lbits: every map entry written in
+// this sample is at least tag, every older one below it.
 __device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv, Shared &sh,
-                                      int w, int src, uint32_t epoch)
+                                      int w, int src, uint32_t tag)
 {
-    const uint32_t old = __hip_atomic_fetch_max(&sv.map[w].stamp, epoch, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (old != epoch) {
+    const uint32_t old =
+        __hip_atomic_fetch_max(&sv.map[w], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (old < tag) {
         const int id = atomicAdd(&sh.tail, 1);
         if (id < a.ws.lcap) {
-            sv.map[w].lid = id;
+            // a later max with tag leaves this larger value in place
+            __hip_atomic_store(&sv.map[w], tag | (uint32_t)(id + 1), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
             LocalVtx rec;
             rec.glob = w;
             rec.par0 = src;
@@ -141,7 +144,7 @@ __device__ __forceinline__ void locate(const Shared &sh, int cnt, int q, int &l,
 }
 
 __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView &sv, Shared &sh,
-                                           uint32_t mask, uint4 col, int src, uint32_t epoch,
+                                           uint32_t mask, uint4 col, int src, uint32_t tag,
                                            uint32_t &live)
 {
     live += (uint32_t)__builtin_popcount(mask);
@@ -149,7 +152,7 @@ __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView
         const int i = __builtin_ctz(mask);
         mask &= mask - 1;
         const uint32_t c = i == 0 ? col.x : i == 1 ? col.y : i == 2 ? col.z : col.w;
-        visit(a, sv, sh, (int)c, src, epoch);
+        visit(a, sv, sh, (int)c, src, tag);
     }
 }
 
@@ -160,7 +163,7 @@ __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView
 // coins comes up live.
 template <bool kLT>
 __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv, Shared &sh,
-                       bool from_seeds, int lo, int hi, uint32_t j, uint32_t epoch,
+                       bool from_seeds, int lo, int hi, uint32_t j, uint32_t tag,
                        uint32_t &scanned, uint32_t &live)
 {
     const int tid = threadIdx.x;
@@ -218,8 +221,8 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
                 if (m1) c1 = c.col4[quad1];
                 if (m2) c2 = c.col4[quad2];
             }
-            visit_mask(a, sv, sh, m1, c1, from_seeds ? 0 : base + l1, epoch, live);
-            visit_mask(a, sv, sh, m2, c2, from_seeds ? 0 : base + l2, epoch, live);
+            visit_mask(a, sv, sh, m1, c1, from_seeds ? 0 : base + l1, tag, live);
+            visit_mask(a, sv, sh, m2, c2, from_seeds ? 0 : base + l2, tag, live);
         }
         __syncthreads();
     }
@@ -255,6 +258,7 @@ void decrease_kernel(DecreaseArgs a)
     sv.lvl = a.ws.lvl + slot * (size_t)(a.ws.lcap + 1);
     sv.extra = a.ws.extra + slot * (size_t)a.ws.xcap;
     uint32_t epoch = a.ws.epoch[slot];
+    const uint32_t emax = 0xFFFFFFFFu >> a.ws.lbits;  // largest epoch the map entries hold
     const uint32_t count = a.sample_list ? *a.sample_count : a.theta;
 
     for (;;) {
@@ -276,7 +280,14 @@ void decrease_kernel(DecreaseArgs a)
             c = Call{I.row_ptr, I.col4,  I.thr4,        I.lo4, I.seeds, I.nseeds,
                      (uint32_t)key, (uint32_t)(key >> 32), I.D,     I.stats};
         }
+        if (epoch >= emax) {
+            // every epoch value is used up: clear this slot's map (the barrier below orders
+            // the stores before the sample's claims) and start again from epoch 1
+            for (int64_t i = tid; i < a.ws.n; i += kBlock) sv.map[i] = 0u;
+            epoch = 0;
+        }
         ++epoch;
+        const uint32_t tag = epoch << a.ws.lbits;
         if (tid == 0) {
             sh.tail = 1;
             sh.nextra = 0;
@@ -295,14 +306,14 @@ void decrease_kernel(DecreaseArgs a)
         __syncthreads();
 
         uint32_t p_scanned = 0, p_live = 0;
-        expand<kLT>(a, c, sv, sh, true, 0, c.nseeds, j, epoch, p_scanned, p_live);
+        expand<kLT>(a, c, sv, sh, true, 0, c.nseeds, j, tag, p_scanned, p_live);
         int L = 1, lo = 1;
         int hi = sh.tail;
         __syncthreads();
         while (lo < hi) {
             if (sh.ovf) break;
             if (tid == 0) sv.lvl[L + 1] = hi;
-            expand<kLT>(a, c, sv, sh, false, lo, hi, j, epoch, p_scanned, p_live);
+            expand<kLT>(a, c, sv, sh, false, lo, hi, j, tag, p_scanned, p_live);
             lo = hi;
             hi = sh.tail;
             ++L;
@@ -327,10 +338,13 @@ void decrease_kernel(DecreaseArgs a)
         const int nX = sh.nextra;
         if (a.reach_only) L = 1;  // reachability alone: no dominators, no counts
 
-        // Extra edges: resolve the target vertex to its local id.
+        // Extra edges: resolve the target vertex to its local id (an L2 read: the entry's
+        // claim was an atomic there).
+        const uint32_t lmask = (1u << a.ws.lbits) - 1u;
         for (int x = tid; x < nX; x += kBlock) {
             int2 e = sv.extra[x];
-            e.y = sv.map[e.y].lid;
+            e.y = (int)(__hip_atomic_load(&sv.map[e.y], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) & lmask) - 1;
             sv.extra[x] = e;
         }
         __syncthreads();

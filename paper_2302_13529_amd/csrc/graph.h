@@ -83,8 +83,6 @@ void free_ws(Workspace &ws);
 // unchanged); cleared on `stream`.
 int alloc_ws(Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap,
              hipStream_t stream);
-// Keep the slots' 32-bit epochs from wrapping over a launch of up to theta samples.
-int guard_epochs(Workspace &ws, uint32_t theta, hipStream_t stream);
 // Validated seed set: distinct seeds ascending, and the seed bitmap.
 int seed_setup(imin_graph *g, const int32_t *S, int32_t nS, std::vector<int32_t> &seeds,
                std::vector<uint32_t> &inelig);
@@ -129,10 +127,9 @@ void multi_free(MultiScratch &ms);
 // [0, total), keys seed + round): the wave kernel, the workgroup kernels for the samples it
 // hands over, then (select) the AdvancedGreedy choice of each instance written to B[slot].
 // Nothing waits for the host. D is cleared first.
-// guarded: the caller has reserved the epochs of this round (no clearing may be issued).
 int multi_round(MultiScratch &ms, const InstanceDesc *inst, int32_t ninst, uint32_t total,
                 uint32_t round, const imin_launch &shape, int num_cus, bool select,
-                int32_t slot, bool lt, hipStream_t stream, bool guarded);
+                int32_t slot, bool lt, hipStream_t stream);
 // The error words of the last rounds (0 when every sample was counted).
 int multi_errors(MultiScratch &ms, uint32_t *wave_err, uint32_t *wg_err, hipStream_t stream);
 

@@ -7,19 +7,21 @@
 namespace imin {
 
 constexpr int kBlock = 1024;  // threads per workgroup; one workgroup works on one sample at a time
+// Workgroup slots per compute unit: as many as its 32 wave slots hold.
+constexpr int kSlotsPerCu = 2048 / kBlock;
 
 // Seeds and blocked vertices: every edge into such a vertex has live threshold 0 in the
 // graph's working threshold array while a call runs, so it is never live, which is exactly
 // the rule that a live edge never activates a seed again or a blocked vertex (Definition 2;
 // each edge's coin is independent of the others). The kernels therefore never test it.
 
-// Per slot and vertex: the epoch of the sample that last reached the vertex, and its
-// local id in that sample. Both halves live in one 8-byte entry so a lookup touches one line;
-// an atomic max with the current epoch claims the vertex.
-struct SlotEntry {
-    uint32_t stamp;
-    int32_t lid;
-};
+// Per slot and vertex, one 32-bit map entry: (epoch << lbits) | (lid + 1), the epoch of the
+// sample that last reached the vertex above its local id in that sample. A sample with
+// epoch t claims a vertex by an atomic max with t << lbits: the entry was below that value
+// exactly when the vertex was not yet reached in this sample. A lid field of 0 means
+// "claimed, local id not yet written"; the claimer writes the id right after. When a slot's
+// epoch reaches the largest value the upper bits hold, the slot clears its own map and
+// starts again from epoch 1.
 
 // Per slot and local vertex (local id 0 is the merged seed): the vertex id, the parent in
 // the BFS spanning tree, the tentative immediate dominator and the subtree size. One
@@ -38,12 +40,12 @@ struct Workspace {
     int64_t n = 0;             // map entries per slot (vertex ids below n)
     int64_t lcap = 0;          // local vertices per sample (root included)
     int64_t xcap = 0;          // non-tree live edges per sample
-    SlotEntry *map = nullptr;  // slots * n
+    uint32_t *map = nullptr;   // slots * n
+    int32_t lbits = 0;         // bits of the local-id field: lcap < 2^lbits, lbits <= 31
     LocalVtx *loc = nullptr;   // slots * lcap
     int32_t *lvl = nullptr;    // slots * (lcap + 1): first local id of each BFS level
     int2 *extra = nullptr;     // slots * xcap: (source local id, target vertex -> local id)
-    uint32_t *epoch = nullptr; // slots
-    uint64_t epochs_used = 0;  // host-side bound on the largest epoch issued so far
+    uint32_t *epoch = nullptr; // slots: epoch of the slot's last sample
     size_t bytes = 0;
 };
 

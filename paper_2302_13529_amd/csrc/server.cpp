@@ -432,7 +432,7 @@ int imin_server_step(imin_server *s, int32_t *n_active, int32_t *n_queued)
                                s->stream)))
             return IMIN_EDEVICE;
         rc = multi_round(s->ms, s->d_table, (int32_t)s->active.size(), total, 0u, s->cfg.launch,
-                         s->g->num_cus, true, 0, s->g->model == IMIN_LT, s->stream, false);
+                         s->g->num_cus, true, 0, s->g->model == IMIN_LT, s->stream);
         if (rc) return rc;
         uint32_t wave_err = 0, wg_err = 0;
         rc = multi_errors(s->ms, &wave_err, &wg_err, s->stream);  // waits for the step

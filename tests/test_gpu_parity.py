@@ -259,3 +259,31 @@ def test_errors_leave_outputs_untouched(gpu, tiny):
     # the handle still works afterwards
     check_decrease(g, t.n, t.row_ptr, t.col, t.prob, t.seeds, None, 50, 1, "after-errors")
     g.close()
+
+
+def _sparse_wide_graph(n=300_000, k=200, seed=3):
+    """A 200-vertex random cluster whose ids are spread over 300,000 vertices; the rest are
+    isolated. The slot maps need 19-bit local ids, leaving 13 epoch bits: a slot exhausts
+    its epochs after 8191 samples and must clear its map."""
+    rng = np.random.default_rng(seed)
+    ids = np.sort(rng.choice(n, k, replace=False))
+    edges = [(int(ids[a]), int(ids[b]), 0.3) for a in range(k)
+             for b in rng.choice(k, 4, replace=False) if a != b]
+    rp, c, p = H.csr_from_edges(n, edges)
+    return n, rp, c, p, [int(ids[0]), int(ids[1])]
+
+
+def test_slot_epochs_wrap(gpu):
+    """One workgroup slot runs 20,000 samples, so its map is cleared twice inside the
+    kernel; a second call continues from the stored epoch. With an extra-edge capacity of 1
+    most samples spill to the two large-capacity slots, whose epochs wrap as well."""
+    n, rp, c, p, seeds = _sparse_wide_graph()
+    g = gpu.Graph(rp, c, p)
+    g.set_small(0)
+    g.set_launch(1, 0)
+    check_decrease(g, n, rp, c, p, seeds, None, 20000, 5, "one slot, epochs wrap")
+    check_decrease(g, n, rp, c, p, seeds, None, 9000, 6, "one slot, second call")
+    g.set_launch(3, 1)
+    _, st = check_decrease(g, n, rp, c, p, seeds, None, 30000, 7, "spill slots, epochs wrap")
+    assert st["spilled"] > 16382
+    g.close()
