@@ -25,7 +25,8 @@ constexpr int32_t kDefaultPickDiv = 4;
 // In automatic mode the wave kernel is dropped for a graph once fewer than this share of
 // a round's samples finished in it.
 constexpr double kSmallKeepShare = 0.5;
-// Workgroup-kernel slots while the wave kernel takes the samples first (it leaves few).
+// Workgroup-kernel slots while the wave kernel takes the samples first (it leaves few); a
+// call whose first round leaves more than that grows them to the full count for the graph.
 constexpr int32_t kSmallModeSlots = 64;
 
 
@@ -526,18 +527,22 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed,
         if (!ok(imin::launch_decrease_small(s, small_grid(g->num_cus, g->small_launch),
                                             g->stream)))
             return IMIN_EDEVICE;
-        if (g->small_mode == -1 && g->auto_pending) {
-            // Automatic policy, first round of the call: when the wave kernel handed over
-            // most samples, the workgroup kernel gets its full slot count now, and the wave
-            // kernel sits out the call's later rounds (results are the same either way).
+        if (g->auto_pending) {
+            // First round of the call. When the wave kernel handed over more samples than
+            // the workgroup kernel has slots, that kernel gets its full slot count now (the
+            // samples it receives are the large ones). In automatic mode, when it handed
+            // over most samples, the wave kernel also sits out the call's later rounds.
+            // Results are the same either way.
             g->auto_pending = false;
             uint32_t handed = 0;
             if (!ok(hipMemcpyAsync(&handed, g->d_sctrl + 1, sizeof(handed),
                                    hipMemcpyDeviceToHost, g->stream)) ||
                 !ok(hipStreamSynchronize(g->stream)))
                 return IMIN_EDEVICE;
-            if ((double)handed > (1.0 - kSmallKeepShare) * (double)theta) {
-                g->small_auto_off = true;
+            const bool drop = g->small_mode == -1 &&
+                              (double)handed > (1.0 - kSmallKeepShare) * (double)theta;
+            if (drop) g->small_auto_off = true;
+            if (drop || handed > (uint32_t)g->main_ws.slots) {
                 rc = size_workspaces(g, 0);
                 if (rc) return rc;
             }

@@ -41,7 +41,7 @@ struct imin_graph {
     int small_mode = -1;                     // wave kernel: -1 automatic, 0 off, 1 on
     bool small_auto_off = false;             // automatic mode: this call's first round found
                                              // most samples too large
-    bool auto_pending = false;               // automatic mode: first round not yet judged
+    bool auto_pending = false;               // wave kernel on: this call's first round not yet judged
     imin_launch small_launch{0, 0, 0};       // 0 fields: defaults
     uint32_t *d_ovf = nullptr;
     uint32_t ovf_cap = 0;
