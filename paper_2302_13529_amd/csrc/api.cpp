@@ -377,14 +377,14 @@ int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uin
     const int64_t lcap = max_n + 1;
     const int64_t xmax = max_m + 1;
     const int64_t xcap = std::min<int64_t>(std::max<int64_t>(4096, lcap / 4), xmax);
-    // kSlotsPerCu workgroup slots per compute unit, as single calls use, within a quarter of the
-    // free memory
+    // kMultiSlotsPerCu workgroup slots per compute unit, within a quarter of the free memory
     size_t free_b = 0, total_b = 0;
     if (!ok(hipMemGetInfo(&free_b, &total_b))) return IMIN_EDEVICE;
     free_b += ms.main_ws.bytes;
     const size_t per = slot_bytes(max_n, lcap, xcap);
     const int32_t slots = (int32_t)std::max<size_t>(
-        1, std::min<size_t>((size_t)imin::kSlotsPerCu * std::max(1, num_cus), (free_b / 4) / per));
+        1, std::min<size_t>((size_t)imin::kMultiSlotsPerCu * std::max(1, num_cus),
+                            (free_b / 4) / per));
     int rc = alloc_ws(ms.main_ws, max_n, slots, lcap, xcap, stream);
     if (rc) return rc;
     if (xcap < xmax) {

@@ -36,7 +36,8 @@
 namespace imin {
 namespace {
 
-// Exclusive prefix sum over the workgroup; *total receives the sum of all values.
+// Exclusive prefix sum over a workgroup of B threads; *total receives the sum of all values.
+template <int B>
 __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *total)
 {
     const int lane = threadIdx.x & 63;
@@ -51,7 +52,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *tot
     __syncthreads();
     int off = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < B / 64; ++w) {
         const int s = s_wave[w];
         off += (w < wid) ? s : 0;
         tot += s;
@@ -81,15 +82,16 @@ struct SlotView {
     int2 *extra;
 };
 
-// Frontier entries per chunk: each thread prepares kPerThread consecutive entries.
+// Frontier entries per chunk: each of the B threads prepares kPerThread consecutive entries.
 constexpr int kPerThread = 4;
-constexpr int kChunk = kBlock * kPerThread;
 
+template <int B>
 struct Shared {
+    static constexpr int kChunk = B * kPerThread;
     int e0[kChunk];
     int e1[kChunk];
     int qpre[kChunk + 1];
-    int wave[kBlock / 64];
+    int wave[B / 64];
     unsigned idx;
     int tail;
     int nextra;
@@ -103,8 +105,9 @@ struct Shared {
 // kept as an extra edge (edges from the merged seed never matter for dominators: their
 // targets are its children). tag = this sample's epoch << lbits: every map entry written in
 // this sample is at least tag, every older one below it.
-__device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv, Shared &sh,
-                                      int w, int src, uint32_t tag)
+template <class Sh>
+__device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv, Sh &sh, int w,
+                                      int src, uint32_t tag)
 {
     const uint32_t old =
         __hip_atomic_fetch_max(&sv.map[w], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -131,7 +134,8 @@ __device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv,
 }
 
 // Quad q of the current chunk: the frontier entry it belongs to and its edge quad index.
-__device__ __forceinline__ void locate(const Shared &sh, int cnt, int q, int &l, int &quad)
+template <class Sh>
+__device__ __forceinline__ void locate(const Sh &sh, int cnt, int q, int &l, int &quad)
 {
     int lo = 0, hi = cnt - 1;
     while (lo < hi) {
@@ -143,7 +147,8 @@ __device__ __forceinline__ void locate(const Shared &sh, int cnt, int q, int &l,
     quad = (sh.e0[lo] >> 2) + (q - sh.qpre[lo]);
 }
 
-__device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView &sv, Shared &sh,
+template <class Sh>
+__device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView &sv, Sh &sh,
                                            uint32_t mask, uint4 col, int src, uint32_t tag,
                                            uint32_t &live)
 {
@@ -157,15 +162,17 @@ __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView
 }
 
 // Expand the frontier [lo, hi): seeds (from_seeds, source = merged root 0) or local ids.
-// The frontier goes in chunks of kChunk entries (kPerThread consecutive entries per thread);
+// The frontier goes in chunks of B * kPerThread entries (kPerThread consecutive entries per
+// thread);
 // the edge quads of a chunk are spread evenly over the workgroup, two independent quads in
 // flight per thread. A quad's thresholds are always read; its targets only when one of its
 // coins comes up live.
-template <bool kLT>
-__device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv, Shared &sh,
+template <int B, bool kLT>
+__device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv, Shared<B> &sh,
                        bool from_seeds, int lo, int hi, uint32_t j, uint32_t tag,
                        uint32_t &scanned, uint32_t &live)
 {
+    constexpr int kChunk = Shared<B>::kChunk;
     const int tid = threadIdx.x;
     for (int base = lo; base < hi; base += kChunk) {
         const int first = tid * kPerThread;
@@ -187,7 +194,7 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
             mine += nq[i];
         }
         int total;
-        int ex = block_exclusive_scan(mine, sh.wave, &total);
+        int ex = block_exclusive_scan<B>(mine, sh.wave, &total);
 #pragma unroll
         for (int i = 0; i < kPerThread; ++i) {
             sh.qpre[first + i] = ex;
@@ -195,8 +202,8 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
         }
         __syncthreads();
         const int cnt = min(kChunk, hi - base);
-        for (int q = tid; q < total; q += 2 * kBlock) {
-            const int q2 = q + kBlock;
+        for (int q = tid; q < total; q += 2 * B) {
+            const int q2 = q + B;
             const bool has2 = q2 < total;
             int l1, quad1, l2, quad2;
             locate(sh, cnt, q, l1, quad1);
@@ -245,11 +252,13 @@ __device__ __forceinline__ void wave_add(unsigned *dst, uint32_t v)
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
 }
 
-template <bool kMulti, bool kLT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+// B threads per workgroup: kBlock for single calls, kMultiBlock for many-instance launches,
+// whose samples are mostly of moderate size and gain more from samples in flight.
+template <bool kMulti, bool kLT, int B = kMulti ? kMultiBlock : kBlock>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void decrease_kernel(DecreaseArgs a)
 {
-    __shared__ Shared sh;
+    __shared__ Shared<B> sh;
     const int tid = threadIdx.x;
     const size_t slot = blockIdx.x;
     SlotView sv;
@@ -283,7 +292,7 @@ void decrease_kernel(DecreaseArgs a)
         if (epoch >= emax) {
             // every epoch value is used up: clear this slot's map (the barrier below orders
             // the stores before the sample's claims) and start again from epoch 1
-            for (int64_t i = tid; i < a.ws.n; i += kBlock) sv.map[i] = 0u;
+            for (int64_t i = tid; i < a.ws.n; i += B) sv.map[i] = 0u;
             epoch = 0;
         }
         ++epoch;
@@ -306,14 +315,14 @@ void decrease_kernel(DecreaseArgs a)
         __syncthreads();
 
         uint32_t p_scanned = 0, p_live = 0;
-        expand<kLT>(a, c, sv, sh, true, 0, c.nseeds, j, tag, p_scanned, p_live);
+        expand<B, kLT>(a, c, sv, sh, true, 0, c.nseeds, j, tag, p_scanned, p_live);
         int L = 1, lo = 1;
         int hi = sh.tail;
         __syncthreads();
         while (lo < hi) {
             if (sh.ovf) break;
             if (tid == 0) sv.lvl[L + 1] = hi;
-            expand<kLT>(a, c, sv, sh, false, lo, hi, j, tag, p_scanned, p_live);
+            expand<B, kLT>(a, c, sv, sh, false, lo, hi, j, tag, p_scanned, p_live);
             lo = hi;
             hi = sh.tail;
             ++L;
@@ -341,7 +350,7 @@ void decrease_kernel(DecreaseArgs a)
         // Extra edges: resolve the target vertex to its local id (an L2 read: the entry's
         // claim was an atomic there).
         const uint32_t lmask = (1u << a.ws.lbits) - 1u;
-        for (int x = tid; x < nX; x += kBlock) {
+        for (int x = tid; x < nX; x += B) {
             int2 e = sv.extra[x];
             e.y = (int)(__hip_atomic_load(&sv.map[e.y], __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT) & lmask) - 1;
@@ -354,13 +363,13 @@ void decrease_kernel(DecreaseArgs a)
         // meanwhile, and is reset to 1 afterwards.
         if (nX > 0) {
             for (;;) {
-                for (int x = tid; x < nX; x += kBlock) {
+                for (int x = tid; x < nX; x += B) {
                     const int v = sv.extra[x].y;
                     sv.loc[v].csz = sv.loc[v].tdom;
                 }
                 if (tid == 0) sh.changed = 0;
                 __syncthreads();
-                for (int x = tid; x < nX; x += kBlock) {
+                for (int x = tid; x < nX; x += B) {
                     const int2 e = sv.extra[x];
                     const int tv = sv.loc[e.y].tdom;
                     const int m1 = nca(sv.loc, tv, e.x);
@@ -371,7 +380,7 @@ void decrease_kernel(DecreaseArgs a)
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
                 __syncthreads();
-                for (int x = tid; x < nX; x += kBlock) {
+                for (int x = tid; x < nX; x += B) {
                     const int v = sv.extra[x].y;
                     const int nv = sv.loc[v].csz;
                     if (nv != sv.loc[v].tdom) {
@@ -384,14 +393,14 @@ void decrease_kernel(DecreaseArgs a)
                 __syncthreads();
                 if (!ch) break;
             }
-            for (int x = tid; x < nX; x += kBlock) sv.loc[sv.extra[x].y].csz = 1;
+            for (int x = tid; x < nX; x += B) sv.loc[sv.extra[x].y].csz = 1;
             __syncthreads();
         }
 
         // Subtree sizes, deepest BFS level first, and the exact accumulation into D.
         for (int l = L - 1; l >= 1; --l) {
             const int b0 = sv.lvl[l], b1 = sv.lvl[l + 1];
-            for (int i = b0 + tid; i < b1; i += kBlock) {
+            for (int i = b0 + tid; i < b1; i += B) {
                 const LocalVtx r = sv.loc[i];
                 if (r.tdom != 0)
                     __hip_atomic_fetch_add(&sv.loc[r.tdom].csz, r.csz, __ATOMIC_RELAXED,
@@ -415,15 +424,15 @@ void decrease_kernel(DecreaseArgs a)
 hipError_t launch_decrease(const DecreaseArgs &a, hipStream_t stream)
 {
     if (a.ws.slots <= 0) return hipErrorInvalidValue;
-    const dim3 grid(a.ws.slots), block(kBlock);
+    const dim3 grid(a.ws.slots);
     if (a.inst && a.lt)
-        hipLaunchKernelGGL((decrease_kernel<true, true>), grid, block, 0, stream, a);
+        hipLaunchKernelGGL((decrease_kernel<true, true>), grid, dim3(kMultiBlock), 0, stream, a);
     else if (a.inst)
-        hipLaunchKernelGGL((decrease_kernel<true, false>), grid, block, 0, stream, a);
+        hipLaunchKernelGGL((decrease_kernel<true, false>), grid, dim3(kMultiBlock), 0, stream, a);
     else if (a.lt)
-        hipLaunchKernelGGL((decrease_kernel<false, true>), grid, block, 0, stream, a);
+        hipLaunchKernelGGL((decrease_kernel<false, true>), grid, dim3(kBlock), 0, stream, a);
     else
-        hipLaunchKernelGGL((decrease_kernel<false, false>), grid, block, 0, stream, a);
+        hipLaunchKernelGGL((decrease_kernel<false, false>), grid, dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 

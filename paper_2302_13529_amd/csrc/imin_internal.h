@@ -6,9 +6,15 @@
 
 namespace imin {
 
-constexpr int kBlock = 1024;  // threads per workgroup; one workgroup works on one sample at a time
+// Threads per workgroup of the workgroup-per-sample kernel (one workgroup works on one sample
+// at a time): single calls, whose samples may be huge, and many-instance launches (batched
+// calls, the server), whose handed-over samples are mostly of moderate size and gain more
+// from having more of them in flight.
+constexpr int kBlock = 1024;
+constexpr int kMultiBlock = 512;
 // Workgroup slots per compute unit: as many as its 32 wave slots hold.
 constexpr int kSlotsPerCu = 2048 / kBlock;
+constexpr int kMultiSlotsPerCu = 2048 / kMultiBlock;
 
 // Seeds and blocked vertices: every edge into such a vertex has live threshold 0 in the
 // graph's working threshold array while a call runs, so it is never live, which is exactly
