@@ -367,12 +367,15 @@ void multi_free(MultiScratch &ms)
     dfree(ms.sj);
     dfree(ms.oi);
     dfree(ms.oj);
+    dfree(ms.part_d);
+    dfree(ms.part_i);
     ms.n = ms.m = 0;
     ms.cap = 0;
+    ms.inst_cap = 0;
 }
 
 int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uint32_t cap,
-                hipStream_t stream)
+                int32_t max_inst, hipStream_t stream)
 {
     const int64_t lcap = max_n + 1;
     const int64_t xmax = max_m + 1;
@@ -407,6 +410,18 @@ int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uin
             return IMIN_ENOMEM;
         }
         ms.cap = cap;
+    }
+    if (max_inst > ms.inst_cap) {
+        dfree(ms.part_d);
+        dfree(ms.part_i);
+        ms.inst_cap = 0;
+        const size_t parts = (size_t)max_inst * imin::kArgParts;
+        if (!ok(hipMalloc(&ms.part_d, parts * sizeof(unsigned long long))) ||
+            !ok(hipMalloc(&ms.part_i, parts * sizeof(int32_t)))) {
+            (void)hipGetLastError();
+            return IMIN_ENOMEM;
+        }
+        ms.inst_cap = max_inst;
     }
     if (!ms.ctrl && !ok(hipMalloc(&ms.ctrl, 7 * sizeof(uint32_t)))) {
         (void)hipGetLastError();
@@ -471,7 +486,11 @@ int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst,
         a.ws = ms.big_ws;
         if (!ok(imin::launch_decrease(a, stream))) return IMIN_EDEVICE;
     }
-    if (select && !ok(imin::launch_batch_argmax(inst, ninst, slot, stream))) return IMIN_EDEVICE;
+    if (select) {
+        if (ninst > ms.inst_cap) return IMIN_ERANGE;
+        if (!ok(imin::launch_batch_argmax(inst, ninst, slot, ms.part_d, ms.part_i, stream)))
+            return IMIN_EDEVICE;
+    }
     return IMIN_OK;
 }
 
@@ -1174,7 +1193,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         max_m = std::max<int64_t>(max_m, it.g->m);
     }
     MultiScratchGuard ms;
-    int rc = multi_alloc(ms.s, g0->num_cus, max_n, max_m, prefix[(size_t)count], bs);
+    int rc = multi_alloc(ms.s, g0->num_cus, max_n, max_m, prefix[(size_t)count], count, bs);
     if (rc) return rc;
     if (!ok(hipMemcpyAsync(d_table.p, table.data(), table.size() * sizeof(imin::InstanceDesc),
                            hipMemcpyHostToDevice, bs)) ||

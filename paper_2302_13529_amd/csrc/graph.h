@@ -119,9 +119,12 @@ struct MultiScratch {
                                //    big next, overflow count, workgroup error
     uint32_t *si = nullptr, *sj = nullptr;  // hand-over list: instance, sample
     uint32_t *oi = nullptr, *oj = nullptr;  // overflow list: instance, sample
+    int32_t inst_cap = 0;                   // instances of the largest round
+    unsigned long long *part_d = nullptr;   // inst_cap * kArgParts partial argmax results
+    int32_t *part_i = nullptr;
 };
 int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uint32_t cap,
-                hipStream_t stream);
+                int32_t max_inst, hipStream_t stream);
 void multi_free(MultiScratch &ms);
 // One round of every instance of the device table inst[0..ninst) (sample indices
 // [0, total), keys seed + round): the wave kernel, the workgroup kernels for the samples it

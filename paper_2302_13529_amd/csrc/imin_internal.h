@@ -190,7 +190,12 @@ hipError_t launch_batch_setup(const InstanceDesc *inst, const BatchStage *st,
 // instance i into out + i * stride (int32 words; counters as pairs of words).
 hipError_t launch_batch_gather(const InstanceDesc *inst, const int32_t *rounds, int32_t *out,
                                int32_t stride, int32_t ninst, hipStream_t stream);
+// The AdvancedGreedy choice of every instance, written to B[slot] and applied (bitmap bit,
+// in-edge masks, *x): kArgParts workgroups per instance scan a share of its D each and
+// leave their best (D, vertex) in part_d/part_i (ninst * kArgParts entries); one workgroup
+// per instance then reduces them.
+constexpr int kArgParts = 16;
 hipError_t launch_batch_argmax(const InstanceDesc *inst, int32_t ninst, int32_t slot,
-                               hipStream_t stream);
+                               unsigned long long *part_d, int32_t *part_i, hipStream_t stream);
 
 }  // namespace imin

@@ -142,29 +142,53 @@ __global__ void batch_zero_kernel(const InstanceDesc *inst)
         I.D[v] = 0ull;
 }
 
-// One workgroup per instance; each thread takes 4 vertices at a time so that several loads
+// Workgroup blockIdx.x scans share blockIdx.x % kArgParts of instance blockIdx.x / kArgParts
+// (a multiple of 4 vertices); each thread takes 4 vertices at a time so that several loads
 // are in flight.
-__global__ void batch_argmax_kernel(const InstanceDesc *inst, int32_t slot)
+__global__ void batch_argmax_part_kernel(const InstanceDesc *inst, unsigned long long *part_d,
+                                         int32_t *part_i)
 {
-    const InstanceDesc &I = inst[blockIdx.x];
+    const InstanceDesc &I = inst[blockIdx.x / kArgParts];
+    const int32_t k = (int32_t)(blockIdx.x % kArgParts);
+    const int32_t per = (((I.n + kArgParts - 1) / kArgParts) + 3) & ~3;
+    const int32_t lo = k * per;
+    const int32_t hi = min(I.n, lo + per);
     unsigned long long bd = 0;
     int bi = -1;
     constexpr int kStep = 4 * kSelBlock;
-    for (int32_t base = 4 * (int32_t)threadIdx.x; base < I.n; base += kStep) {
+    for (int32_t base = lo + 4 * (int32_t)threadIdx.x; base < hi; base += kStep) {
         unsigned long long d[4];
         uint32_t w[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int32_t v = base + k;
-            d[k] = v < I.n ? I.D[v] : 0ull;
-            w[k] = v < I.n ? I.inelig[v >> 5] : 0xFFFFFFFFu;
+            d[k] = v < hi ? I.D[v] : 0ull;
+            w[k] = v < hi ? I.inelig[v >> 5] : 0xFFFFFFFFu;
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int32_t v = base + k;
-            if (v < I.n && !((w[k] >> (v & 31)) & 1u)) better(bd, bi, d[k], (int)v);
+            if (v < hi && !((w[k] >> (v & 31)) & 1u)) better(bd, bi, d[k], (int)v);
         }
     }
+    block_best(bd, bi);
+    if (threadIdx.x == 0) {
+        part_d[blockIdx.x] = bd;
+        part_i[blockIdx.x] = bi;
+    }
+}
+
+// One workgroup per instance: the best of its kArgParts shares, applied.
+__global__ void batch_argmax_apply_kernel(const InstanceDesc *inst,
+                                          const unsigned long long *part_d,
+                                          const int32_t *part_i, int32_t slot)
+{
+    const InstanceDesc &I = inst[blockIdx.x];
+    unsigned long long bd = 0;
+    int bi = -1;
+    if (threadIdx.x < kArgParts)
+        better(bd, bi, part_d[blockIdx.x * kArgParts + threadIdx.x],
+               part_i[blockIdx.x * kArgParts + threadIdx.x]);
     block_best(bd, bi);
     if (threadIdx.x == 0) {
         if (bi >= 0) {
@@ -294,10 +318,13 @@ hipError_t launch_batch_zero(const InstanceDesc *inst, int32_t ninst, hipStream_
 }
 
 hipError_t launch_batch_argmax(const InstanceDesc *inst, int32_t ninst, int32_t slot,
-                               hipStream_t stream)
+                               unsigned long long *part_d, int32_t *part_i, hipStream_t stream)
 {
     if (ninst <= 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_argmax_kernel, dim3(ninst), dim3(kSelBlock), 0, stream, inst, slot);
+    hipLaunchKernelGGL(batch_argmax_part_kernel, dim3(ninst * kArgParts), dim3(kSelBlock), 0,
+                       stream, inst, part_d, part_i);
+    hipLaunchKernelGGL(batch_argmax_apply_kernel, dim3(ninst), dim3(kSelBlock), 0, stream, inst,
+                       part_d, part_i, slot);
     return hipGetLastError();
 }
 

@@ -359,7 +359,7 @@ int imin_server_create(imin_graph *g, const imin_server_config *cfg, imin_server
         return IMIN_ENOMEM;
     }
     int rc = multi_alloc(s->ms, g->num_cus, g->n, g->m, (uint32_t)c.max_active * c.max_theta,
-                         s->stream);
+                         c.max_active, s->stream);
     size_t cap = 0;
     if (!rc) rc = ensure_dev(s->d_table, cap, (size_t)c.max_active);
     cap = 0;
