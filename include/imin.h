@@ -187,7 +187,7 @@ IMIN_API int imin_set_launch(imin_graph *g, int32_t slots, int64_t extra_cap);
  *                 so waves beyond what fits on a unit start as others finish).
  *   quad_limit    a 64-vertex frontier chunk with more 4-edge quads than this is left to
  *                 the workgroup kernel (default 2048). The seed level is exempt when its
- *                 rows fit the kernel's 128-quad seed cache.
+ *                 rows fit the kernel's 256-quad seed cache.
  *   pick_div      waves take runs of consecutive samples of about a 1/pick_div share of
  *                 what remains per wave, between 4 and 64 samples (default 4).
  *   graph         imin_greedy_batch only: 1 captures all rounds of the call into one HIP

@@ -29,7 +29,7 @@ namespace {
 constexpr int kSW = kSmallWaves;
 constexpr int kSmallBlock = kSW * 64;
 constexpr int kMaxSmallJacobiRounds = 4 * kSmallV;
-constexpr int kSeedSlots = 2;                      // cached seed quads per lane
+constexpr int kSeedSlots = 4;                      // cached seed quads per lane
 constexpr int kSeedCacheQuads = 64 * kSeedSlots;
 constexpr uint32_t kPickMin = 4;                   // samples per work-counter update: a
 constexpr uint32_t kPickMax = 64;                  // share of what remains, within these
