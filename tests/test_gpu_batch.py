@@ -226,3 +226,23 @@ def test_batch_degenerate_instances(gpu):
     assert list(B) == list(res[4][0])
     for g in graphs:
         g.close()
+
+
+def test_batch_argmax_ties_across_shares(gpu):
+    """The batched argmax scans each instance's counts in 16 shares; two hubs with equal
+    counts in different shares must resolve to the smaller id, as the oracle does."""
+    n, h1, h2 = 50_000, 40_000, 45_000
+    edges = [(0, h1, 1.0), (0, h2, 1.0)]
+    edges += [(h1, h1 + 1 + k, 1.0) for k in range(100)]
+    edges += [(h2, h2 + 1 + k, 1.0) for k in range(100)]
+    edges += [(7, 8, 0.5), (8, 9, 0.5)]  # a second component, unreachable from the seed
+    rp, c, p = H.csr_from_edges(n, edges)
+    g = gpu.Graph(rp, c, p)
+    case("two equal hubs in different argmax shares")
+    (B, st), = gpu.imin_greedy_batch([(g.handle, [0], 3, 20, 4)])
+    Bo, calls, so = orc.greedy(n, rp, c, p, np.asarray([0], np.int32), 3, 20, 4, 0)
+    assert list(B) == list(Bo)
+    assert list(B)[:2] == [h1, h2]
+    Bp, _ = g.greedy([0], 3, 20, 4, gpu.IMIN_AG)
+    assert list(Bp) == list(B)
+    g.close()
