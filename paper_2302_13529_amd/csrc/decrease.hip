@@ -362,6 +362,33 @@ void decrease_kernel(DecreaseArgs a)
         // The subtree-size field of such a vertex holds the next tentative dominator
         // meanwhile, and is reset to 1 afterwards.
         if (nX > 0) {
+            // First one Gauss-Seidel sweep: the extra edges in list order (roughly the BFS
+            // order of their sources), B at a time, each chunk one step over its targets on
+            // the tree the earlier chunks left. A step over some vertices and some of their
+            // predecessors keeps every dominator of v on v's tree path (a dominator of v
+            // dominates each predecessor) and only moves t(v) up, so the Jacobi rounds below
+            // still end at the dominator tree; they just have less left to change.
+            for (int x0 = 0; x0 < nX; x0 += B) {
+                const int x = x0 + tid;
+                int2 e = make_int2(0, 0);
+                if (x < nX) {
+                    e = sv.extra[x];
+                    sv.loc[e.y].csz = sv.loc[e.y].tdom;
+                }
+                __syncthreads();
+                if (x < nX) {
+                    const int tv = sv.loc[e.y].tdom;
+                    const int m1 = nca(sv.loc, tv, e.x);
+                    const int m2 = nca(sv.loc, tv, sv.loc[e.y].par0);
+                    const int mm = min(m1, m2);
+                    if (mm < tv)
+                        __hip_atomic_fetch_min(&sv.loc[e.y].csz, mm, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                __syncthreads();
+                if (x < nX) sv.loc[e.y].tdom = sv.loc[e.y].csz;
+                __syncthreads();
+            }
             for (;;) {
                 for (int x = tid; x < nX; x += B) {
                     const int v = sv.extra[x].y;
