@@ -116,7 +116,9 @@ struct InstanceDesc {
     int32_t *B;               // blocker slots (batched greedy)
     int32_t *x;               // the last round's winner (batched greedy)
     const uint4 *thr_orig;    // thresholds as created (batched set-up restores from them)
-    uint32_t *ctrl;           // the graph's 4 control words of the workgroup kernel
+    uint32_t *ctrl;           // 4 control words: the graph's workgroup-kernel counters in
+                              // single calls; in many-instance launches 0 = skip the wave
+                              // kernel, 1 = its hand-overs this round, 3 = error
     int32_t nseeds;
     int32_t n;
     int32_t nquads;           // quads of thr4

@@ -178,7 +178,10 @@ __global__ void batch_argmax_part_kernel(const InstanceDesc *inst, unsigned long
     }
 }
 
-// One workgroup per instance: the best of its kArgParts shares, applied.
+// One workgroup per instance: the best of its kArgParts shares, applied. It also ends the
+// instance's round for the wave kernel: when that kernel handed over more than half of the
+// instance's samples (control word 1), later rounds send them straight to the workgroup
+// kernel (control word 0).
 __global__ void batch_argmax_apply_kernel(const InstanceDesc *inst,
                                           const unsigned long long *part_d,
                                           const int32_t *part_i, int32_t slot)
@@ -191,6 +194,8 @@ __global__ void batch_argmax_apply_kernel(const InstanceDesc *inst,
                part_i[blockIdx.x * kArgParts + threadIdx.x]);
     block_best(bd, bi);
     if (threadIdx.x == 0) {
+        if (2ull * I.ctrl[1] > (unsigned long long)I.theta) I.ctrl[0] = 1u;
+        I.ctrl[1] = 0u;
         if (bi >= 0) {
             I.inelig[bi >> 5] |= 1u << (bi & 31);
             I.B[slot] = bi;

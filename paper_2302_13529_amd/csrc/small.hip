@@ -485,6 +485,7 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
     int cur = -1;
     InstanceDesc I{};
     uint32_t cur_lo = 0, cur_hi = 0;
+    bool skip = false;  // the current instance's samples go straight to the large kernel
     SeedCache sc;
     sc.total = -1;
     Tally tally{0, 0, 0, 0};
@@ -519,13 +520,35 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
                 I = a.inst[cur];
                 cur_lo = I.sample_base;
                 cur_hi = I.sample_base + I.theta;
-                if (kLT) sc.total = -1;  // vertex-keyed choices: no per-quad seed cache
+                // Many-instance launches: an instance whose previous round handed most of
+                // its samples over (control word 0, set by the round's argmax) skips this
+                // kernel; the results do not depend on which kernel runs a sample.
+                skip = a.spill_inst &&
+                       __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                           &I.ctrl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0u;
+                if (kLT || skip) sc.total = -1;  // LT: vertex-keyed choices, no quad cache
                 else build_seed_cache(I, ws, sc);
             }
             const uint32_t j = idx - cur_lo;
+            if (skip) {
+                // the rest of the run within this instance, listed at once
+                const uint32_t cnt = min(last, cur_hi) - idx;
+                uint32_t pos = 0;
+                if (lane == 0) pos = atomicAdd(a.spill_count, cnt);
+                pos = __builtin_amdgcn_readfirstlane(__shfl(pos, 0, 64));
+                for (uint32_t k = (uint32_t)lane; k < cnt; k += 64) {
+                    a.spill_inst[pos + k] = (uint32_t)cur;
+                    a.spill_j[pos + k] = j + k;
+                }
+                idx += cnt - 1;
+                continue;
+            }
             if (!run_sample<kLT>(a, I, sc, ws, j, tally) && lane == 0) {
                 const uint32_t pos = atomicAdd(a.spill_count, 1u);
-                if (a.spill_inst) a.spill_inst[pos] = (uint32_t)cur;
+                if (a.spill_inst) {
+                    a.spill_inst[pos] = (uint32_t)cur;
+                    atomicAdd(&I.ctrl[1], 1u);  // this round's hand-overs of the instance
+                }
                 a.spill_j[pos] = j;
             }
         }

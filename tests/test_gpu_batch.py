@@ -145,9 +145,11 @@ def test_batch_with_handed_over_samples_and_existing_scratch(gpu, batch16):
         B, st = res[i]
         assert list(B) == list(Bo), i
         assert st["reached"] == so["reached"], i
-    # round 0 of the path reaches 299 vertices in every sample (all handed over); once its
-    # first vertex is blocked nothing is reached and the wave kernel finishes the rest
-    assert res[0][1]["wave_samples"] == 3 * 60
+    # round 0 of the path reaches 299 vertices in every sample (all handed over), so its
+    # later rounds skip the wave kernel and go straight to the workgroup kernel; the tiny
+    # graph's samples stay in the wave kernel
+    assert res[0][1]["wave_samples"] == 0 and res[0][1]["samples"] == 4 * 60
+    assert res[2][1]["wave_samples"] > 0
     # the handles keep working for plain calls afterwards
     case("plain decrease after the batch")
     D, _ = gdense.decrease([0], None, 50, 0)
