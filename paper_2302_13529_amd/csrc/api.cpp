@@ -520,13 +520,35 @@ int launch_large(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t key,
 int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed, uint32_t call,
                    bool reach_only = false)
 {
+    int rc = IMIN_OK;
+    if (g->probe == 1) {
+        // Automatic mode, second round of a call that kept the wave kernel: a timed trial of
+        // the workgroup kernel alone, at its full slot count.
+        g->small_auto_off = true;
+        rc = size_workspaces(g, 0);
+        if (rc) return rc;
+    } else if (g->probe == 2) {
+        // The call keeps whichever form ran its round faster (results are the same).
+        g->probe = 0;
+        const size_t a = g->probe_kev[0], b = g->probe_kev[1];
+        float with = 0.0f, without = 0.0f;
+        if (!ok(hipEventSynchronize(g->kev[b + 1])) ||
+            !ok(hipEventElapsedTime(&with, g->kev[a], g->kev[a + 1])) ||
+            !ok(hipEventElapsedTime(&without, g->kev[b], g->kev[b + 1])))
+            return IMIN_EDEVICE;
+        g->small_auto_off = without < with;
+    }
     const bool small = small_enabled(g);
     if ((!reach_only && !ok(imin::launch_fill_u64(g->d_D, g->n, 0, g->stream))) ||
         (small && !ok(imin::launch_fill_u32(g->d_sctrl, 2, 0, g->stream))))
         return IMIN_EDEVICE;
     hipEvent_t k0, k1;
-    int rc = kernel_events(g, &k0, &k1);
+    rc = kernel_events(g, &k0, &k1);
     if (rc) return rc;
+    if (g->probe == 1) {
+        g->probe = 2;
+        g->probe_kev[1] = g->kev_used - 2;
+    }
     if (!ok(hipEventRecord(k0, g->stream))) return IMIN_EDEVICE;
     if (small) {
         imin::SmallArgs s;
@@ -561,6 +583,11 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed,
             const bool drop = g->small_mode == -1 &&
                               (double)handed > (1.0 - kSmallKeepShare) * (double)theta;
             if (drop) g->small_auto_off = true;
+            if (g->small_mode == -1 && !drop && !reach_only) {
+                // kept: the next round runs as a timed trial without the wave kernel
+                g->probe = 1;
+                g->probe_kev[0] = g->kev_used - 2;
+            }
             if (drop || handed > (uint32_t)g->main_ws.slots) {
                 rc = size_workspaces(g, 0);
                 if (rc) return rc;
@@ -612,6 +639,7 @@ int begin_call(imin_graph *g)
     g->kev_used = 0;
     g->small_auto_off = false;  // every call tries the wave kernel in its first round
     g->auto_pending = true;
+    g->probe = 0;
     if (!ok(hipEventRecord(g->ev0, g->stream))) return IMIN_EDEVICE;
     return IMIN_OK;
 }

@@ -42,6 +42,10 @@ struct imin_graph {
     bool small_auto_off = false;             // automatic mode: this call's first round found
                                              // most samples too large
     bool auto_pending = false;               // wave kernel on: this call's first round not yet judged
+    int probe = 0;                           // automatic mode, per call: 1 = the next round is a
+                                             // trial without the wave kernel, 2 = the trial ran,
+                                             // 0 = nothing to compare
+    size_t probe_kev[2] = {0, 0};            // kev index of the timed rounds (with, without)
     imin_launch small_launch{0, 0, 0};       // 0 fields: defaults
     uint32_t *d_ovf = nullptr;
     uint32_t ovf_cap = 0;
