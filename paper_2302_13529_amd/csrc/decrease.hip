@@ -222,6 +222,12 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
                 m2 = has2 ? live_mask_lt(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], b2,
                                          t2, c2)
                           : 0u;
+            } else if (B == kMultiBlock) {
+                // many-instance launches: targets loaded beside the thresholds
+                c1 = c.col4[quad1];
+                c2 = c.col4[quad2];
+                m1 = live_mask(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], t1);
+                m2 = has2 ? live_mask(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], t2) : 0u;
             } else {
                 m1 = live_mask(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], t1);
                 m2 = has2 ? live_mask(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], t2) : 0u;
