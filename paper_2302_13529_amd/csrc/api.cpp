@@ -45,20 +45,24 @@ void free_ws(Workspace &ws)
     dfree(ws.loc);
     dfree(ws.lvl);
     dfree(ws.extra);
+    dfree(ws.rng);
     dfree(ws.epoch);
     ws = Workspace();
 }
 
-size_t slot_bytes(int64_t n, int64_t lcap, int64_t xcap)
+size_t slot_bytes(int64_t n, int64_t lcap, int64_t xcap, bool rng = false)
 {
     return (size_t)n * sizeof(uint32_t) + (size_t)lcap * sizeof(imin::LocalVtx) +
-           (size_t)(lcap + 1) * sizeof(int32_t) + (size_t)xcap * sizeof(int2) + sizeof(uint32_t);
+           (size_t)(lcap + 1) * sizeof(int32_t) + (size_t)xcap * sizeof(int2) + sizeof(uint32_t) +
+           (rng ? (size_t)lcap * sizeof(int2) : 0);
 }
 
 int alloc_ws(Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap,
-             hipStream_t stream)
+             hipStream_t stream, bool rng)
 {
-    if (ws.slots == slots && ws.n == n && ws.lcap == lcap && ws.xcap == xcap) return IMIN_OK;
+    if (ws.slots == slots && ws.n == n && ws.lcap == lcap && ws.xcap == xcap &&
+        (ws.rng != nullptr) == rng)
+        return IMIN_OK;
     free_ws(ws);
     // the map's local-id field holds lid + 1 <= lcap, and leaves at least one epoch bit
     int32_t lbits = 1;
@@ -69,6 +73,7 @@ int alloc_ws(Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap
                 ok(hipMalloc(&ws.loc, S * (size_t)lcap * sizeof(imin::LocalVtx))) &&
                 ok(hipMalloc(&ws.lvl, S * (size_t)(lcap + 1) * sizeof(int32_t))) &&
                 ok(hipMalloc(&ws.extra, S * (size_t)std::max<int64_t>(xcap, 1) * sizeof(int2))) &&
+                (!rng || ok(hipMalloc(&ws.rng, S * (size_t)lcap * sizeof(int2)))) &&
                 ok(hipMalloc(&ws.epoch, S * sizeof(uint32_t)));
     if (!good) {
         free_ws(ws);
@@ -85,7 +90,7 @@ int alloc_ws(Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap
     ws.lcap = lcap;
     ws.xcap = xcap;
     ws.lbits = lbits;
-    ws.bytes = S * slot_bytes(n, lcap, xcap);
+    ws.bytes = S * slot_bytes(n, lcap, xcap, rng);
     return IMIN_OK;
 }
 
@@ -118,10 +123,10 @@ int size_workspaces(imin_graph *g, int32_t max_slots)
             (have >= slots || (max_slots == 0 && have > kSmallModeSlots)))
             slots = have;
     }
-    int rc = alloc_ws(g->main_ws, g->n, slots, lcap, xcap, g->stream);
+    int rc = alloc_ws(g->main_ws, g->n, slots, lcap, xcap, g->stream, false);
     if (rc) return rc;
     if (xcap < xmax) {
-        rc = alloc_ws(g->big_ws, g->n, kSpillSlots, lcap, xmax, g->stream);
+        rc = alloc_ws(g->big_ws, g->n, kSpillSlots, lcap, xmax, g->stream, false);
         if (rc) return rc;
     } else {
         free_ws(g->big_ws);
@@ -384,14 +389,14 @@ int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uin
     size_t free_b = 0, total_b = 0;
     if (!ok(hipMemGetInfo(&free_b, &total_b))) return IMIN_EDEVICE;
     free_b += ms.main_ws.bytes;
-    const size_t per = slot_bytes(max_n, lcap, xcap);
+    const size_t per = slot_bytes(max_n, lcap, xcap, true);
     const int32_t slots = (int32_t)std::max<size_t>(
         1, std::min<size_t>((size_t)imin::kMultiSlotsPerCu * std::max(1, num_cus),
                             (free_b / 4) / per));
-    int rc = alloc_ws(ms.main_ws, max_n, slots, lcap, xcap, stream);
+    int rc = alloc_ws(ms.main_ws, max_n, slots, lcap, xcap, stream, true);
     if (rc) return rc;
     if (xcap < xmax) {
-        rc = alloc_ws(ms.big_ws, max_n, (int32_t)kSpillSlots, lcap, xmax, stream);
+        rc = alloc_ws(ms.big_ws, max_n, (int32_t)kSpillSlots, lcap, xmax, stream, true);
         if (rc) return rc;
     } else {
         free_ws(ms.big_ws);

@@ -76,6 +76,7 @@ struct Call {
 };
 
 struct SlotView {
+    int2 *rng;  // many-instance launches: row range of each local vertex
     uint32_t *map;
     LocalVtx *loc;
     int32_t *lvl;
@@ -105,10 +106,14 @@ struct Shared {
 // kept as an extra edge (edges from the merged seed never matter for dominators: their
 // targets are its children). tag = this sample's epoch << lbits: every map entry written in
 // this sample is at least tag, every older one below it.
-template <class Sh>
+// kRng: w's row range is read beside the claim, so that the next level starts from it
+// without a dependent row_ptr read.
+template <bool kRng, class Sh>
 __device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv, Sh &sh, int w,
-                                      int src, uint32_t tag)
+                                      int src, uint32_t tag, const int32_t *row_ptr)
 {
+    int2 r = make_int2(0, 0);
+    if (kRng) r = make_int2(row_ptr[w], row_ptr[w + 1]);
     const uint32_t old =
         __hip_atomic_fetch_max(&sv.map[w], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (old < tag) {
@@ -123,6 +128,7 @@ __device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv,
             rec.tdom = src;
             rec.csz = 1;
             sv.loc[id] = rec;
+            if (kRng) sv.rng[id] = r;
         } else {
             sh.ovf = 1;
         }
@@ -147,17 +153,17 @@ __device__ __forceinline__ void locate(const Sh &sh, int cnt, int q, int &l, int
     quad = (sh.e0[lo] >> 2) + (q - sh.qpre[lo]);
 }
 
-template <class Sh>
+template <bool kRng, class Sh>
 __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView &sv, Sh &sh,
                                            uint32_t mask, uint4 col, int src, uint32_t tag,
-                                           uint32_t &live)
+                                           uint32_t &live, const int32_t *row_ptr)
 {
     live += (uint32_t)__builtin_popcount(mask);
     while (mask) {
         const int i = __builtin_ctz(mask);
         mask &= mask - 1;
         const uint32_t c = i == 0 ? col.x : i == 1 ? col.y : i == 2 ? col.z : col.w;
-        visit(a, sv, sh, (int)c, src, tag);
+        visit<kRng>(a, sv, sh, (int)c, src, tag, row_ptr);
     }
 }
 
@@ -167,7 +173,7 @@ __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView
 // the edge quads of a chunk are spread evenly over the workgroup, two independent quads in
 // flight per thread. A quad's thresholds are always read; its targets only when one of its
 // coins comes up live.
-template <int B, bool kLT>
+template <int B, bool kLT, bool kRng>
 __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv, Shared<B> &sh,
                        bool from_seeds, int lo, int hi, uint32_t j, uint32_t tag,
                        uint32_t &scanned, uint32_t &live)
@@ -183,9 +189,16 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
             const int k = base + first + i;
             nq[i] = 0;
             if (k < hi) {
-                const int v = from_seeds ? c.seeds[k] : sv.loc[k].glob;
-                const int e0 = c.row_ptr[v];
-                const int e1 = c.row_ptr[v + 1];
+                int e0, e1;
+                if (kRng && !from_seeds) {
+                    const int2 r = sv.rng[k];
+                    e0 = r.x;
+                    e1 = r.y;
+                } else {
+                    const int v = from_seeds ? c.seeds[k] : sv.loc[k].glob;
+                    e0 = c.row_ptr[v];
+                    e1 = c.row_ptr[v + 1];
+                }
                 scanned += (uint32_t)(e1 - e0);
                 nq[i] = (e1 > e0) ? (((e1 - 1) >> 2) - (e0 >> 2) + 1) : 0;
                 sh.e0[first + i] = e0;
@@ -234,8 +247,8 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
                 if (m1) c1 = c.col4[quad1];
                 if (m2) c2 = c.col4[quad2];
             }
-            visit_mask(a, sv, sh, m1, c1, from_seeds ? 0 : base + l1, tag, live);
-            visit_mask(a, sv, sh, m2, c2, from_seeds ? 0 : base + l2, tag, live);
+            visit_mask<kRng>(a, sv, sh, m1, c1, from_seeds ? 0 : base + l1, tag, live, c.row_ptr);
+            visit_mask<kRng>(a, sv, sh, m2, c2, from_seeds ? 0 : base + l2, tag, live, c.row_ptr);
         }
         __syncthreads();
     }
@@ -272,6 +285,7 @@ void decrease_kernel(DecreaseArgs a)
     sv.loc = a.ws.loc + slot * (size_t)a.ws.lcap;
     sv.lvl = a.ws.lvl + slot * (size_t)(a.ws.lcap + 1);
     sv.extra = a.ws.extra + slot * (size_t)a.ws.xcap;
+    sv.rng = kMulti ? a.ws.rng + slot * (size_t)a.ws.lcap : nullptr;
     uint32_t epoch = a.ws.epoch[slot];
     const uint32_t emax = 0xFFFFFFFFu >> a.ws.lbits;  // largest epoch the map entries hold
     const uint32_t count = a.sample_list ? *a.sample_count : a.theta;
@@ -321,14 +335,14 @@ void decrease_kernel(DecreaseArgs a)
         __syncthreads();
 
         uint32_t p_scanned = 0, p_live = 0;
-        expand<B, kLT>(a, c, sv, sh, true, 0, c.nseeds, j, tag, p_scanned, p_live);
+        expand<B, kLT, kMulti>(a, c, sv, sh, true, 0, c.nseeds, j, tag, p_scanned, p_live);
         int L = 1, lo = 1;
         int hi = sh.tail;
         __syncthreads();
         while (lo < hi) {
             if (sh.ovf) break;
             if (tid == 0) sv.lvl[L + 1] = hi;
-            expand<B, kLT>(a, c, sv, sh, false, lo, hi, j, tag, p_scanned, p_live);
+            expand<B, kLT, kMulti>(a, c, sv, sh, false, lo, hi, j, tag, p_scanned, p_live);
             lo = hi;
             hi = sh.tail;
             ++L;

@@ -84,9 +84,10 @@ void dfree(T *&p)
 
 void free_ws(Workspace &ws);
 // Scratch of `slots` workgroup-kernel slots with maps of n entries (kept when the shape is
-// unchanged); cleared on `stream`.
+// unchanged); cleared on `stream`. rng: with the per-local-vertex row ranges that the
+// many-instance kernel keeps.
 int alloc_ws(Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap,
-             hipStream_t stream);
+             hipStream_t stream, bool rng);
 // Validated seed set: distinct seeds ascending, and the seed bitmap.
 int seed_setup(imin_graph *g, const int32_t *S, int32_t nS, std::vector<int32_t> &seeds,
                std::vector<uint32_t> &inelig);

@@ -51,6 +51,8 @@ struct Workspace {
     LocalVtx *loc = nullptr;   // slots * lcap
     int32_t *lvl = nullptr;    // slots * (lcap + 1): first local id of each BFS level
     int2 *extra = nullptr;     // slots * xcap: (source local id, target vertex -> local id)
+    int2 *rng = nullptr;       // slots * lcap, many-instance workspaces only: the row range
+                               // (row_ptr pair) of each local vertex, read when it is claimed
     uint32_t *epoch = nullptr; // slots: epoch of the slot's last sample
     size_t bytes = 0;
 };
