@@ -229,7 +229,10 @@ def bench_served(args) -> dict:
     queries = gg.served_queries(inst.n)[: args.queries]
     g = binding.Graph(inst.row_ptr, inst.col, inst.prob)
     budget = int(args.hbm_gib * (1 << 30))
-    srv = binding.Server(g, hbm_budget=budget, max_active=args.max_active, max_theta=10000)
+    launch = {k: v for k, v in dict(waves_per_cu=args.waves_per_cu, quad_limit=args.quad_limit,
+                                    pick_div=args.pick_div).items() if v}
+    srv = binding.Server(g, hbm_budget=budget, max_active=args.max_active, max_theta=10000,
+                         launch=launch or None)
     # plain form: one imin_greedy call per query, on a bounded prefix of the mix
     plain_n = min(args.plain_queries, len(queries))
     print(f"[bench] plain: warmup + {plain_n} queries", file=sys.stderr, flush=True)
@@ -273,6 +276,7 @@ def bench_served(args) -> dict:
         "config": {"workload": inst.name, "n": inst.n, "m": inst.m, "queries": len(queries),
                    "step": "one server step: a greedy round of every admitted query",
                    "hbm_budget_gib": args.hbm_gib, "max_active": args.max_active,
+                   "launch": launch,
                    "parallelism": "none"},
         "plain_value": plain_samples / plain_s,
         "plain_queries": plain_n,
