@@ -309,7 +309,7 @@ def main() -> int:
     ap.add_argument("--plain-queries", type=int, default=40,
                     help="served: queries timed one plain call at a time")
     ap.add_argument("--hbm-gib", type=float, default=16.0, help="served: query-state budget")
-    ap.add_argument("--max-active", type=int, default=128, help="served: admitted at once")
+    ap.add_argument("--max-active", type=int, default=256, help="served: admitted at once")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--quad-limit", type=int, default=0)
     ap.add_argument("--pick-div", type=int, default=0)
