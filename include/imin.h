@@ -239,6 +239,9 @@ typedef struct {
  * wave-per-sample launch over all their samples (samples that outgrow it go to the
  * workgroup kernel of their own graph), then one argmax per instance. Instance i's result
  * is bit-identical to imin_greedy(inst[i].g, S, nS, b, theta, seed, IMIN_AG, ...).
+ * The batch's device scratch (workgroup slots sized for its largest instance, hand-over
+ * lists) stays with inst[0].g after the call and serves the next batch that graph leads;
+ * imin_graph_destroy releases it.
  *   mode    IMIN_AG only (IMIN_EINVAL otherwise).
  *   count   >= 1; the total of theta over the batch must not exceed 2^31 (IMIN_ERANGE).
  *   launch  the wave kernel's launch shape (NULL: defaults); the graphs' own imin_set_small

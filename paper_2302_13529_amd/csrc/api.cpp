@@ -654,6 +654,11 @@ void destroy(imin_graph *g)
     if (!g) return;
     (void)hipSetDevice(g->device);
     if (g->stream) (void)hipStreamSynchronize(g->stream);
+    if (g->batch_ms) {
+        multi_free(*g->batch_ms);
+        delete g->batch_ms;
+        g->batch_ms = nullptr;
+    }
     free_ws(g->main_ws);
     free_ws(g->big_ws);
     dfree(g->d_row_ptr);
@@ -742,12 +747,6 @@ struct GraphCapture {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
     }
-};
-
-// Frees a many-instance scratch when the call ends, however it ends.
-struct MultiScratchGuard {
-    MultiScratch s;
-    ~MultiScratchGuard() { multi_free(s); }
 };
 
 }  // namespace host
@@ -1225,9 +1224,18 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         max_n = std::max<int64_t>(max_n, it.g->n);
         max_m = std::max<int64_t>(max_m, it.g->m);
     }
-    MultiScratchGuard ms;
-    int rc = multi_alloc(ms.s, g0->num_cus, max_n, max_m, prefix[(size_t)count], count, bs);
-    if (rc) return rc;
+    // The batch's scratch stays with its first graph for the next batch that graph leads
+    // (same shape: nothing is allocated or cleared again).
+    if (!g0->batch_ms) {
+        g0->batch_ms = new (std::nothrow) MultiScratch();
+        if (!g0->batch_ms) return IMIN_ENOMEM;
+    }
+    MultiScratch &ms = *g0->batch_ms;
+    int rc = multi_alloc(ms, g0->num_cus, max_n, max_m, prefix[(size_t)count], count, bs);
+    if (rc) {
+        multi_free(ms);
+        return rc;
+    }
     if (!ok(hipMemcpyAsync(d_table.p, table.data(), table.size() * sizeof(imin::InstanceDesc),
                            hipMemcpyHostToDevice, bs)) ||
         !ok(hipMemcpyAsync(d_stages.p, stages.data(), stages.size() * sizeof(imin::BatchStage),
@@ -1249,7 +1257,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         int32_t act = count;
         for (int32_t r = 0; r < max_rounds; ++r) {
             while (act > 0 && items[(size_t)act - 1].rounds <= r) --act;
-            rc = multi_round(ms.s, d_table.p, act, prefix[(size_t)act], (uint32_t)r, shape,
+            rc = multi_round(ms, d_table.p, act, prefix[(size_t)act], (uint32_t)r, shape,
                              g0->num_cus, true, r, lt, bs);
             if (rc) return rc;
         }
@@ -1269,7 +1277,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
             rc = kernel_events(g0, &k0, &k1);
             if (rc) return rc;
             if (!ok(hipEventRecord(k0, bs))) return IMIN_EDEVICE;
-            rc = multi_round(ms.s, d_table.p, active, prefix[(size_t)active], (uint32_t)r,
+            rc = multi_round(ms, d_table.p, active, prefix[(size_t)active], (uint32_t)r,
                              shape, g0->num_cus, true, r, lt, bs);
             if (rc) return rc;
             if (!ok(hipEventRecord(k1, bs))) return IMIN_EDEVICE;
@@ -1284,7 +1292,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         !ok(hipEventRecord(g0->ev1, bs)) || !ok(hipEventSynchronize(g0->ev1)))
         return IMIN_EDEVICE;
     uint32_t wave_err = 0, wg_err = 0;
-    rc = multi_errors(ms.s, &wave_err, &wg_err, bs);
+    rc = multi_errors(ms, &wave_err, &wg_err, bs);
     if (rc) return rc;
     if (wave_err || wg_err) return IMIN_EDEVICE;
     std::vector<std::vector<int32_t>> B((size_t)count);

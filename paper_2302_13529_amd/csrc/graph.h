@@ -7,6 +7,12 @@
 
 #include <vector>
 
+namespace imin {
+namespace host {
+struct MultiScratch;
+}  // namespace host
+}  // namespace imin
+
 struct imin_graph {
     int device = 0;
     int32_t n = 0;
@@ -62,6 +68,8 @@ struct imin_graph {
     int32_t *d_list = nullptr;         // 2n: device copies of the two lists above
     std::vector<hipEvent_t> kev;  // pairs around each decrease launch of the current call
     size_t kev_used = 0;
+    imin::host::MultiScratch *batch_ms = nullptr;  // scratch of the batches this graph leads
+                                                   // (first instance), kept for the next one
     int32_t force_slots = 0;
     int64_t force_xcap = 0;
 };
