@@ -248,3 +248,22 @@ def test_batch_argmax_ties_across_shares(gpu):
     Bp, _ = g.greedy([0], 3, 20, 4, gpu.IMIN_AG)
     assert list(Bp) == list(B)
     g.close()
+
+
+def test_batch_scratch_kept_across_shapes(gpu, batch16):
+    """The first graph of a batch keeps the batch's scratch; later batches it leads, larger
+    or smaller, reuse or resize it and give the same results as plain calls."""
+    small, big = batch16[0], max(batch16, key=lambda t: t.n)
+    gs = gpu.Graph(small.row_ptr, small.col, small.prob)
+    gb = gpu.Graph(big.row_ptr, big.col, big.prob)
+    shapes = [[(gs, small, 3, 200)], [(gs, small, 3, 200), (gb, big, 2, 300)],
+              [(gs, small, 2, 150)], [(gs, small, 3, 200)]]
+    for k, shape in enumerate(shapes):
+        case(f"batch {k} led by the same graph: {len(shape)} instance(s)")
+        probs = [(g.handle, t.seeds, b, th, t.seed) for g, t, b, th in shape]
+        res = gpu.imin_greedy_batch(probs)
+        for (g, t, b, th), (B, st) in zip(shape, res):
+            Bp, sp = g.greedy(t.seeds, b, th, t.seed, gpu.IMIN_AG)
+            assert list(B) == list(Bp) and st["reached"] == sp["reached"]
+    gs.close()
+    gb.close()
