@@ -208,9 +208,9 @@ typedef struct {
  * sample kernel in the same call.
  *   enable  -1 automatic (the default: on for the first round of every call, and off for
  *           the call's later rounds when fewer than half of the first round's samples
- *           finished in the wave kernel; otherwise the second round runs without it as a
- *           timed trial, and later rounds keep whichever of the two rounds was faster),
- *           0 off, 1 on.
+ *           finished in the wave kernel; otherwise the second round is timed with it, the
+ *           third runs without it as a timed trial, and later rounds keep whichever of the
+ *           two was faster), 0 off, 1 on.
  *   launch  the wave kernel's launch shape (NULL: defaults).
  * Results never depend on these values. Errors: IMIN_EINVAL for NULL g, enable outside
  * [-1, 1], or negative launch values.

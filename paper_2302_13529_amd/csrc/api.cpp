@@ -526,13 +526,13 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed,
                    bool reach_only = false)
 {
     int rc = IMIN_OK;
-    if (g->probe == 1) {
-        // Automatic mode, second round of a call that kept the wave kernel: a timed trial of
-        // the workgroup kernel alone, at its full slot count.
+    if (g->probe == 2) {
+        // Automatic mode, a call that kept the wave kernel: after a timed round with it, a
+        // timed trial round of the workgroup kernel alone, at its full slot count.
         g->small_auto_off = true;
         rc = size_workspaces(g, 0);
         if (rc) return rc;
-    } else if (g->probe == 2) {
+    } else if (g->probe == 3) {
         // The call keeps whichever form ran its round faster (results are the same).
         g->probe = 0;
         const size_t a = g->probe_kev[0], b = g->probe_kev[1];
@@ -550,9 +550,9 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed,
     hipEvent_t k0, k1;
     rc = kernel_events(g, &k0, &k1);
     if (rc) return rc;
-    if (g->probe == 1) {
-        g->probe = 2;
-        g->probe_kev[1] = g->kev_used - 2;
+    if (g->probe == 1 || g->probe == 2) {
+        g->probe_kev[g->probe - 1] = g->kev_used - 2;
+        ++g->probe;
     }
     if (!ok(hipEventRecord(k0, g->stream))) return IMIN_EDEVICE;
     if (small) {
@@ -589,9 +589,9 @@ int decrease_round(imin_graph *g, int32_t nseeds, uint32_t theta, uint64_t seed,
                               (double)handed > (1.0 - kSmallKeepShare) * (double)theta;
             if (drop) g->small_auto_off = true;
             if (g->small_mode == -1 && !drop && !reach_only) {
-                // kept: the next round runs as a timed trial without the wave kernel
+                // kept: the next round is timed with the wave kernel (this one waited for
+                // the host), the one after it without
                 g->probe = 1;
-                g->probe_kev[0] = g->kev_used - 2;
             }
             if (drop || handed > (uint32_t)g->main_ws.slots) {
                 rc = size_workspaces(g, 0);

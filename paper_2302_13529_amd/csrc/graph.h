@@ -48,9 +48,9 @@ struct imin_graph {
     bool small_auto_off = false;             // automatic mode: this call's first round found
                                              // most samples too large
     bool auto_pending = false;               // wave kernel on: this call's first round not yet judged
-    int probe = 0;                           // automatic mode, per call: 1 = the next round is a
-                                             // trial without the wave kernel, 2 = the trial ran,
-                                             // 0 = nothing to compare
+    int probe = 0;                           // automatic mode, per call: 1 = time the next
+                                             // round (wave kernel on), 2 = the next round is a
+                                             // timed trial without it, 3 = compare; 0 = none
     size_t probe_kev[2] = {0, 0};            // kev index of the timed rounds (with, without)
     imin_launch small_launch{0, 0, 0};       // 0 fields: defaults
     uint32_t *d_ovf = nullptr;
