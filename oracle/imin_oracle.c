@@ -43,6 +43,7 @@
  * live-edge worlds (Lemma 1, Theorem 4) and the paper's toy-graph numbers (Examples 1-4,
  * Table III), the greedy drivers against brute-force greedy on deterministic graphs.
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -111,6 +112,14 @@ int orc_edge_live(uint64_t key, uint32_t j, int64_t e, float p)
     return edge_live(key, j, e, orc_threshold(p));
 }
 
+/* Upper end of an in-edge's 24-bit interval from the fp64 running sum of the weights up to
+ * and including that edge: min(2^24, ceil(2^24 * sum)). */
+static double lt_bound(double sum)
+{
+    double bound = ceil(sum * 16777216.0);
+    return bound > 16777216.0 ? 16777216.0 : bound;
+}
+
 /* LT: the in-edge of u chosen in sample j (its triggering set), or -1 for none. */
 static int64_t lt_trigger(const int32_t *in_ptr, const int32_t *in_edge, const float *w,
                           uint64_t key, uint32_t j, int32_t u)
@@ -123,9 +132,7 @@ static int64_t lt_trigger(const int32_t *in_ptr, const int32_t *in_edge, const f
     double sum = 0.0;
     for (int32_t i = in_ptr[u]; i < in_ptr[u + 1]; ++i) {
         sum += (double)w[in_edge[i]];
-        double bound = ceil(sum * 16777216.0);
-        if (bound > 16777216.0) bound = 16777216.0;
-        if (R < bound) return in_edge[i];
+        if (R < lt_bound(sum)) return in_edge[i];
     }
     return -1;
 }
@@ -592,6 +599,150 @@ static int decrease_into(orc_state *st, uint32_t theta, uint64_t key, uint64_t *
     return ORC_OK;
 }
 
+/* ---------------------------------------------------------------- threaded variant */
+
+/*
+ * Algorithm 2 draws its sampled graphs independently of one another and only adds integers
+ * into the counts, so the samples may run on several host threads, in any order, with the
+ * same result. Thread t of T takes the samples j = t, t + T, t + 2T, ... with a scratch
+ * state and uint64 counts of its own; counts and work counters are summed once every thread
+ * is done. A pool of one thread is decrease_into itself. This variant exists to check large
+ * configurations in reasonable time; tests pin it equal to the single-threaded function.
+ */
+#define ORC_MAX_THREADS 256
+
+typedef struct {
+    orc_state *st;
+    uint32_t theta, t, T;
+    uint64_t key;
+    uint64_t *counts;   /* n entries, this thread's own */
+    uint64_t stats[4];
+    int rc;
+} mt_part;
+
+static void *mt_part_run(void *arg)
+{
+    mt_part *p = (mt_part *)arg;
+    orc_state *st = p->st;
+    for (int32_t v = 0; v < st->n; ++v) p->counts[v] = 0;
+    uint64_t reached = 0, samples = 0;
+    st->edges_scanned = 0;
+    st->live_edges = 0;
+    p->rc = ORC_OK;
+    for (uint64_t j = p->t; j < p->theta; j += p->T) {
+        int rc = one_sample(st, p->key, (uint32_t)j);
+        if (rc) { p->rc = rc; return NULL; }
+        for (int32_t w = 1; w < st->nloc; ++w)
+            p->counts[st->glob[st->vert[w]]] += (uint64_t)st->size[w];
+        reached += (uint64_t)(st->nloc - 1);
+        samples++;
+        reset_loc(st);
+    }
+    p->stats[0] = samples;
+    p->stats[1] = reached;
+    p->stats[2] = st->edges_scanned;
+    p->stats[3] = st->live_edges;
+    return NULL;
+}
+
+typedef struct {
+    int T;
+    orc_state *st;    /* T states over the same problem */
+    uint64_t *part;   /* (T - 1) * n counts of threads 1 .. T-1 */
+} orc_pool;
+
+static void pool_free(orc_pool *pl)
+{
+    if (pl->st)
+        for (int t = 0; t < pl->T; ++t) state_free(&pl->st[t]);
+    free(pl->st);
+    free(pl->part);
+    memset(pl, 0, sizeof(*pl));
+}
+
+static int pool_init(orc_pool *pl, int T, int32_t n, const int32_t *row_ptr, const int32_t *col,
+                     const float *prob, const int32_t *S, int32_t nS, int model)
+{
+    memset(pl, 0, sizeof(*pl));
+    if (T < 1 || T > ORC_MAX_THREADS) return ORC_EINVAL;
+    pl->st = (orc_state *)calloc((size_t)T, sizeof(orc_state));
+    if (!pl->st) return ORC_ENOMEM;
+    for (int t = 0; t < T; ++t) {
+        int rc = state_init(&pl->st[t], n, row_ptr, col, prob, S, nS, model);
+        if (rc) { pl->T = t; pool_free(pl); return rc; }
+        pl->T = t + 1;
+    }
+    if (T > 1) {
+        pl->part = (uint64_t *)malloc((size_t)(T - 1) * (size_t)n * sizeof(uint64_t));
+        if (!pl->part) { pool_free(pl); return ORC_ENOMEM; }
+    }
+    return ORC_OK;
+}
+
+static void pool_set_blocked(orc_pool *pl, const uint8_t *blocked)
+{
+    for (int t = 0; t < pl->T; ++t) pl->st[t].blocked = blocked;
+}
+
+/* Algorithm 2 on the pool's threads: the same counts and stats as decrease_into. */
+static int pool_decrease(orc_pool *pl, uint32_t theta, uint64_t key, uint64_t *counts,
+                         uint64_t *stats)
+{
+    uint32_t T = (uint32_t)pl->T < theta ? (uint32_t)pl->T : theta;
+    if (T <= 1) return decrease_into(&pl->st[0], theta, key, counts, stats);
+    const int32_t n = pl->st[0].n;
+    mt_part parts[ORC_MAX_THREADS];
+    pthread_t th[ORC_MAX_THREADS];
+    int started[ORC_MAX_THREADS];
+    for (uint32_t t = 0; t < T; ++t) {
+        memset(&parts[t], 0, sizeof(parts[t]));
+        parts[t].st = &pl->st[t];
+        parts[t].theta = theta;
+        parts[t].t = t;
+        parts[t].T = T;
+        parts[t].key = key;
+        parts[t].counts = t == 0 ? counts : pl->part + (size_t)(t - 1) * (size_t)n;
+        started[t] = 0;
+    }
+    int rc = ORC_OK;
+    for (uint32_t t = 1; t < T; ++t) {
+        if (pthread_create(&th[t], NULL, mt_part_run, &parts[t]) != 0) { rc = ORC_ENOMEM; break; }
+        started[t] = 1;
+    }
+    if (!rc) mt_part_run(&parts[0]);
+    for (uint32_t t = 1; t < T; ++t)
+        if (started[t]) pthread_join(th[t], NULL);
+    if (rc) return rc;
+    uint64_t tot[4] = {0, 0, 0, 0};
+    for (uint32_t t = 0; t < T; ++t) {
+        if (parts[t].rc) return parts[t].rc;
+        for (int k = 0; k < 4; ++k) tot[k] += parts[t].stats[k];
+    }
+    for (uint32_t t = 1; t < T; ++t) {
+        const uint64_t *c = parts[t].counts;
+        for (int32_t v = 0; v < n; ++v) counts[v] += c[v];
+    }
+    if (stats)
+        for (int k = 0; k < 4; ++k) stats[k] = tot[k];
+    return ORC_OK;
+}
+
+/* Algorithm 2 as orc_decrease_m, its samples spread over nthreads host threads. */
+int orc_decrease_mt(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
+                    const int32_t *S, int32_t nS, const uint8_t *blocked, uint32_t theta,
+                    uint64_t key, uint64_t *counts, uint64_t *stats, int model, int nthreads)
+{
+    if (theta == 0 || !counts) return ORC_EINVAL;
+    orc_pool pl;
+    int rc = pool_init(&pl, nthreads, n, row_ptr, col, prob, S, nS, model);
+    if (rc) return rc;
+    pool_set_blocked(&pl, blocked);
+    rc = check_blocked(&pl.st[0]);
+    if (!rc) rc = pool_decrease(&pl, theta, key, counts, stats);
+    pool_free(&pl);
+    return rc;
+}
+
 int64_t orc_sample(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
                    const int32_t *S, int32_t nS, const uint8_t *blocked, uint64_t key,
                    uint32_t j, int32_t *c_out, int32_t *idom_out)
@@ -641,6 +792,29 @@ int64_t orc_lt_trigger(int32_t n, const int32_t *row_ptr, const int32_t *col, co
     return e;
 }
 
+/* LT: the interval upper ends bound_1, bound_2, ... of u's in-edges in ascending edge id
+ * (the values lt_trigger compares against), written to bounds[]; returns their count. */
+int64_t orc_lt_bounds(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *w,
+                      int32_t u, uint32_t *bounds)
+{
+    if (u < 0 || u >= n || !bounds) return ORC_EINVAL;
+    orc_state st;
+    memset(&st, 0, sizeof(st));
+    if (check_graph(n, row_ptr, col, w)) return ORC_EINVAL;
+    st.n = n;
+    st.row_ptr = row_ptr;
+    st.col = col;
+    if (build_in_edges(&st, row_ptr[n])) { state_free(&st); return ORC_ENOMEM; }
+    double sum = 0.0;
+    int64_t k = 0;
+    for (int32_t i = st.in_ptr[u]; i < st.in_ptr[u + 1]; ++i) {
+        sum += (double)w[st.in_edge[i]];
+        bounds[k++] = (uint32_t)lt_bound(sum);
+    }
+    state_free(&st);
+    return k;
+}
+
 #define ORC_AG 0
 #define ORC_GR 1
 
@@ -653,37 +827,39 @@ int64_t orc_lt_trigger(int32_t n, const int32_t *row_ptr, const int32_t *col, co
  * blockers[] receives the slots in order; *n_blockers their count; calls_out the number
  * of calls of Algorithm 2 made; stats accumulate over all calls.
  */
-int orc_greedy_m(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
-                 const int32_t *S, int32_t nS, int32_t b, uint32_t theta, uint64_t seed,
-                 int32_t mode, int32_t *blockers, int32_t *n_blockers, int32_t *calls_out,
-                 uint64_t *stats, int model)
+int orc_greedy_mt(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
+                  const int32_t *S, int32_t nS, int32_t b, uint32_t theta, uint64_t seed,
+                  int32_t mode, int32_t *blockers, int32_t *n_blockers, int32_t *calls_out,
+                  uint64_t *stats, int model, int nthreads);
+
+static int greedy_core(orc_pool *pl, const int32_t *row_ptr, const int32_t *col, int32_t b,
+                       uint32_t theta, uint64_t seed, int32_t mode, int32_t *blockers,
+                       int32_t *n_blockers, int32_t *calls_out, uint64_t *stats)
 {
-    if (theta == 0 || b < 0 || !blockers || !n_blockers) return ORC_EINVAL;
-    if (mode != ORC_AG && mode != ORC_GR) return ORC_EINVAL;
-    orc_state st;
+    orc_state *st = &pl->st[0];
+    const int32_t n = st->n;
     uint64_t tot[4] = {0, 0, 0, 0}, one[4];
     uint64_t call = 0;
     int32_t nb = 0;
-    int rc = state_init(&st, n, row_ptr, col, prob, S, nS, model);
-    if (rc) return rc;
+    int rc = ORC_OK;
     uint8_t *blk = (uint8_t *)calloc((size_t)n, 1);
     uint64_t *D = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
     uint8_t *cand = (uint8_t *)calloc((size_t)n, 1);
     int32_t *B = (int32_t *)malloc((size_t)(b > 0 ? b : 1) * sizeof(int32_t));
     int32_t *snap = (int32_t *)malloc((size_t)(b > 0 ? b : 1) * sizeof(int32_t));
     if (!blk || !D || !cand || !B || !snap) { rc = ORC_ENOMEM; goto done; }
-    st.blocked = blk;
+    pool_set_blocked(pl, blk);
     if (mode == ORC_AG) {
-        int32_t nonseed = n - st.nseeds;
+        int32_t nonseed = n - st->nseeds;
         int32_t rounds = b < nonseed ? b : nonseed;
         for (int32_t r = 0; r < rounds; ++r) {
-            rc = decrease_into(&st, theta, seed + call, D, one);
+            rc = pool_decrease(pl, theta, seed + call, D, one);
             if (rc) goto done;
             call++;
             for (int k = 0; k < 4; ++k) tot[k] += one[k];
             int32_t x = -1;
             for (int32_t u = 0; u < n; ++u) {
-                if (st.is_seed[u] || blk[u]) continue;
+                if (st->is_seed[u] || blk[u]) continue;
                 if (x == -1 || D[u] > D[x]) x = u;
             }
             blk[x] = 1;
@@ -692,16 +868,16 @@ int orc_greedy_m(int32_t n, const int32_t *row_ptr, const int32_t *col, const fl
     } else {
         /* CB = out-neighbours of the merged seed, seeds excluded */
         int32_t ncb = 0;
-        for (int32_t i = 0; i < st.nseeds; ++i) {
-            int32_t s = st.seeds[i];
+        for (int32_t i = 0; i < st->nseeds; ++i) {
+            int32_t s = st->seeds[i];
             for (int64_t e = row_ptr[s]; e < row_ptr[s + 1]; ++e) {
                 int32_t v = col[e];
-                if (!st.is_seed[v] && !cand[v]) { cand[v] = 1; ncb++; }
+                if (!st->is_seed[v] && !cand[v]) { cand[v] = 1; ncb++; }
             }
         }
         int32_t k = ncb < b ? ncb : b;
         for (int32_t r = 0; r < k; ++r) {
-            rc = decrease_into(&st, theta, seed + call, D, one);
+            rc = pool_decrease(pl, theta, seed + call, D, one);
             if (rc) goto done;
             call++;
             for (int q = 0; q < 4; ++q) tot[q] += one[q];
@@ -721,13 +897,13 @@ int orc_greedy_m(int32_t n, const int32_t *row_ptr, const int32_t *col, const fl
             for (int32_t q = 0; q < nb; ++q)
                 if (B[q] == u) slot = q;
             blk[u] = 0;
-            rc = decrease_into(&st, theta, seed + call, D, one);
+            rc = pool_decrease(pl, theta, seed + call, D, one);
             if (rc) goto done;
             call++;
             for (int q = 0; q < 4; ++q) tot[q] += one[q];
             int32_t x = -1;
             for (int32_t v = 0; v < n; ++v) {
-                if (st.is_seed[v] || blk[v]) continue;
+                if (st->is_seed[v] || blk[v]) continue;
                 if (x == -1 || D[v] > D[x]) x = v;
             }
             B[slot] = x;
@@ -741,8 +917,34 @@ int orc_greedy_m(int32_t n, const int32_t *row_ptr, const int32_t *col, const fl
     if (stats) for (int q = 0; q < 4; ++q) stats[q] = tot[q];
     rc = ORC_OK;
 done:
+    pool_set_blocked(pl, NULL);
     free(blk); free(D); free(cand); free(B); free(snap);
-    state_free(&st);
+    return rc;
+}
+
+int orc_greedy_m(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
+                 const int32_t *S, int32_t nS, int32_t b, uint32_t theta, uint64_t seed,
+                 int32_t mode, int32_t *blockers, int32_t *n_blockers, int32_t *calls_out,
+                 uint64_t *stats, int model)
+{
+    return orc_greedy_mt(n, row_ptr, col, prob, S, nS, b, theta, seed, mode, blockers,
+                         n_blockers, calls_out, stats, model, 1);
+}
+
+/* The greedy drivers with every Algorithm 2 call spread over nthreads host threads. */
+int orc_greedy_mt(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *prob,
+                  const int32_t *S, int32_t nS, int32_t b, uint32_t theta, uint64_t seed,
+                  int32_t mode, int32_t *blockers, int32_t *n_blockers, int32_t *calls_out,
+                  uint64_t *stats, int model, int nthreads)
+{
+    if (theta == 0 || b < 0 || !blockers || !n_blockers) return ORC_EINVAL;
+    if (mode != ORC_AG && mode != ORC_GR) return ORC_EINVAL;
+    orc_pool pl;
+    int rc = pool_init(&pl, nthreads, n, row_ptr, col, prob, S, nS, model);
+    if (rc) return rc;
+    rc = greedy_core(&pl, row_ptr, col, b, theta, seed, mode, blockers, n_blockers, calls_out,
+                     stats);
+    pool_free(&pl);
     return rc;
 }
 

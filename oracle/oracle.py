@@ -25,7 +25,7 @@ def build() -> str:
     """Compile the checker with gcc (plain C99, -O2) next to its source."""
     tmp = _LIB + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
-                           "-o", tmp, _SRC, "-lm"])
+                           "-pthread", "-o", tmp, _SRC, "-lm"])
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -62,6 +62,12 @@ def _load():
     lib.orc_greedy.restype = ctypes.c_int
     lib.orc_greedy_m.argtypes = lib.orc_greedy.argtypes + [ctypes.c_int]
     lib.orc_greedy_m.restype = ctypes.c_int
+    lib.orc_decrease_mt.argtypes = lib.orc_decrease_m.argtypes + [ctypes.c_int]
+    lib.orc_decrease_mt.restype = ctypes.c_int
+    lib.orc_greedy_mt.argtypes = lib.orc_greedy_m.argtypes + [ctypes.c_int]
+    lib.orc_greedy_mt.restype = ctypes.c_int
+    lib.orc_lt_bounds.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32, P]
+    lib.orc_lt_bounds.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -122,16 +128,32 @@ def sample(n, row_ptr, col, prob, seeds, blocked, key: int, j: int, model: int =
     return int(r), c, idom
 
 
-def decrease(n, row_ptr, col, prob, seeds, blocked, theta: int, key: int, model: int = IC):
-    """Integer decrease counts D[n] and stats (samples, reached, edges scanned, live edges)."""
+def lt_bounds(n, row_ptr, col, w, u: int):
+    """LT: the interval upper ends of u's in-edges, ascending edge id (orc_lt_bounds)."""
+    row_ptr, col, w = _graph(row_ptr, col, w)
+    out = np.zeros(max(1, int(np.count_nonzero(col == u))), dtype=np.uint32)
+    k = _load().orc_lt_bounds(n, _ptr(row_ptr), _ptr(col), _ptr(w), u, _ptr(out))
+    if k < 0:
+        raise OracleError(f"orc_lt_bounds failed: {k}")
+    return out[:k].copy()
+
+
+def decrease(n, row_ptr, col, prob, seeds, blocked, theta: int, key: int, model: int = IC,
+             threads: int = 1):
+    """Integer decrease counts D[n] and stats (samples, reached, edges scanned, live edges).
+    threads > 1: the samples spread over that many host threads (same result)."""
     lib = _load()
     row_ptr, col, prob = _graph(row_ptr, col, prob)
     S = np.ascontiguousarray(seeds, dtype=np.int32)
     blk = None if blocked is None else np.ascontiguousarray(blocked, dtype=np.uint8)
     D = np.zeros(n, dtype=np.uint64)
     st = np.zeros(4, dtype=np.uint64)
-    rc = lib.orc_decrease_m(n, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(S), S.shape[0],
-                            _ptr(blk), theta, key, _ptr(D), _ptr(st), model)
+    if threads > 1:
+        rc = lib.orc_decrease_mt(n, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(S), S.shape[0],
+                                 _ptr(blk), theta, key, _ptr(D), _ptr(st), model, threads)
+    else:
+        rc = lib.orc_decrease_m(n, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(S), S.shape[0],
+                                _ptr(blk), theta, key, _ptr(D), _ptr(st), model)
     if rc != 0:
         raise OracleError(f"orc_decrease failed: {rc}")
     return D, dict(samples=int(st[0]), reached=int(st[1]), edges_scanned=int(st[2]),
@@ -139,8 +161,9 @@ def decrease(n, row_ptr, col, prob, seeds, blocked, theta: int, key: int, model:
 
 
 def greedy(n, row_ptr, col, prob, seeds, b: int, theta: int, seed: int, mode: int,
-           model: int = IC):
-    """Blocker slots in order, number of decrease calls, summed stats."""
+           model: int = IC, threads: int = 1):
+    """Blocker slots in order, number of decrease calls, summed stats.
+    threads > 1: every decrease call spread over that many host threads (same result)."""
     lib = _load()
     row_ptr, col, prob = _graph(row_ptr, col, prob)
     S = np.ascontiguousarray(seeds, dtype=np.int32)
@@ -148,8 +171,14 @@ def greedy(n, row_ptr, col, prob, seeds, b: int, theta: int, seed: int, mode: in
     nb = np.zeros(1, dtype=np.int32)
     calls = np.zeros(1, dtype=np.int32)
     st = np.zeros(4, dtype=np.uint64)
-    rc = lib.orc_greedy_m(n, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(S), S.shape[0], b,
-                          theta, seed, mode, _ptr(out), _ptr(nb), _ptr(calls), _ptr(st), model)
+    if threads > 1:
+        rc = lib.orc_greedy_mt(n, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(S), S.shape[0], b,
+                               theta, seed, mode, _ptr(out), _ptr(nb), _ptr(calls), _ptr(st),
+                               model, threads)
+    else:
+        rc = lib.orc_greedy_m(n, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(S), S.shape[0], b,
+                              theta, seed, mode, _ptr(out), _ptr(nb), _ptr(calls), _ptr(st),
+                              model)
     if rc != 0:
         raise OracleError(f"orc_greedy failed: {rc}")
     return out[: nb[0]].copy(), int(calls[0]), dict(samples=int(st[0]), reached=int(st[1]),
