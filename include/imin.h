@@ -79,8 +79,11 @@ typedef struct {
     double device_ms;       /* GPU time of the whole call, measured with HIP events */
     double kernel_ms;       /* GPU time of the sampling/dominator kernel launches alone,
                                summed over the call (HIP events around each launch) */
-    uint64_t wave_samples;  /* samples finished by the one-wave-per-sample kernel (the rest
-                               ran one workgroup per sample) */
+    uint64_t wave_samples;  /* samples finished by a wavefront-level kernel (one sample per
+                               wave, or several per wave); the rest ran one workgroup per
+                               sample */
+    uint64_t pack_samples;  /* of those, samples finished by the kernel that runs several
+                               samples per wavefront (batched calls and the server) */
 } imin_stats;
 
 /*

@@ -32,7 +32,8 @@ class imin_stats(ctypes.Structure):
     _fields_ = [("samples", ctypes.c_uint64), ("reached", ctypes.c_uint64),
                 ("edges_scanned", ctypes.c_uint64), ("live_edges", ctypes.c_uint64),
                 ("spilled", ctypes.c_uint64), ("device_ms", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double), ("wave_samples", ctypes.c_uint64)]
+                ("kernel_ms", ctypes.c_double), ("wave_samples", ctypes.c_uint64),
+                ("pack_samples", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -22,6 +22,13 @@ constexpr uint32_t kSpillSlots = 2;
 constexpr int32_t kDefaultSmallWavesPerCu = 20;
 constexpr int32_t kDefaultQuadLimit = 2048;
 constexpr int32_t kDefaultPickDiv = 4;
+// Packed kernel: a frontier vertex with more edge quads than this hands its sample over.
+constexpr int32_t kDefaultPackQuadLimit = 256;
+// Packed kernel workgroups per compute unit: as many as its LDS allows (kPackWaves waves of
+// kPackG samples each per workgroup).
+constexpr int kPackGroupsPerCu = 3;
+
+int pack_grid(int num_cus) { return std::max(1, num_cus) * kPackGroupsPerCu; }
 // In automatic mode the wave kernel is dropped for a graph once fewer than this share of
 // a round's samples finished in it.
 constexpr double kSmallKeepShare = 0.5;
@@ -368,6 +375,8 @@ void multi_free(MultiScratch &ms)
     free_ws(ms.main_ws);
     free_ws(ms.big_ws);
     dfree(ms.ctrl);
+    dfree(ms.pi);
+    dfree(ms.pj);
     dfree(ms.si);
     dfree(ms.sj);
     dfree(ms.oi);
@@ -402,12 +411,16 @@ int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uin
         free_ws(ms.big_ws);
     }
     if (cap > ms.cap) {
+        dfree(ms.pi);
+        dfree(ms.pj);
         dfree(ms.si);
         dfree(ms.sj);
         dfree(ms.oi);
         dfree(ms.oj);
         ms.cap = 0;
-        if (!ok(hipMalloc(&ms.si, (size_t)cap * sizeof(uint32_t))) ||
+        if (!ok(hipMalloc(&ms.pi, (size_t)cap * sizeof(uint32_t))) ||
+            !ok(hipMalloc(&ms.pj, (size_t)cap * sizeof(uint32_t))) ||
+            !ok(hipMalloc(&ms.si, (size_t)cap * sizeof(uint32_t))) ||
             !ok(hipMalloc(&ms.sj, (size_t)cap * sizeof(uint32_t))) ||
             !ok(hipMalloc(&ms.oi, (size_t)cap * sizeof(uint32_t))) ||
             !ok(hipMalloc(&ms.oj, (size_t)cap * sizeof(uint32_t)))) {
@@ -428,11 +441,11 @@ int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uin
         }
         ms.inst_cap = max_inst;
     }
-    if (!ms.ctrl && !ok(hipMalloc(&ms.ctrl, 7 * sizeof(uint32_t)))) {
+    if (!ms.ctrl && !ok(hipMalloc(&ms.ctrl, kMultiCtrl * sizeof(uint32_t)))) {
         (void)hipGetLastError();
         return IMIN_ENOMEM;
     }
-    if (!ok(imin::launch_fill_u32(ms.ctrl, 7, 0, stream))) return IMIN_EDEVICE;
+    if (!ok(imin::launch_fill_u32(ms.ctrl, kMultiCtrl, 0, stream))) return IMIN_EDEVICE;
     ms.n = max_n;
     ms.m = max_m;
     return IMIN_OK;
@@ -444,13 +457,39 @@ int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst,
 {
     if (total > ms.cap) return IMIN_ERANGE;
     const bool spill = ms.big_ws.slots > 0;
-    // words 0, 1, 3, 4, 5 restart every round; the error words 2 and 6 accumulate
+    // words 0, 1, 3, 4, 5, 7, 8 restart every round; the error words 2 and 6 accumulate
     if (!ok(imin::launch_batch_zero(inst, ninst, stream)) ||
         !ok(imin::launch_fill_u32(ms.ctrl, 2, 0, stream)) ||
-        !ok(imin::launch_fill_u32(ms.ctrl + 3, 3, 0, stream)))
+        !ok(imin::launch_fill_u32(ms.ctrl + 3, 3, 0, stream)) ||
+        !ok(imin::launch_fill_u32(ms.ctrl + 7, 2, 0, stream)))
         return IMIN_EDEVICE;
+    // The smallest samples first, several to a wavefront (independent cascade only: the
+    // packed kernel keeps the seed level's edge coins in registers); what outgrows it goes
+    // to the one-sample-per-wave kernel through a device-side list.
+    const bool pack = !lt;
+    if (pack) {
+        imin::PackArgs p;
+        std::memset(&p, 0, sizeof(p));
+        p.inst = inst;
+        p.ninst = ninst;
+        p.total = total;
+        p.round = round;
+        p.quad_limit = kDefaultPackQuadLimit;
+        p.pick_div = shape.pick_div > 0 ? shape.pick_div : kDefaultPickDiv;
+        p.next = ms.ctrl + 7;
+        p.out_inst = ms.pi;
+        p.out_j = ms.pj;
+        p.out_count = ms.ctrl + 8;
+        p.error = ms.ctrl + 2;
+        if (!ok(imin::launch_decrease_pack(p, pack_grid(num_cus), stream))) return IMIN_EDEVICE;
+    }
     imin::SmallArgs s;
     std::memset(&s, 0, sizeof(s));
+    if (pack) {
+        s.in_inst = ms.pi;
+        s.in_j = ms.pj;
+        s.in_count = ms.ctrl + 8;
+    }
     s.inst = inst;
     s.ninst = ninst;
     s.total = total;
@@ -626,6 +665,7 @@ int finish_call(imin_graph *g, imin_stats *stats)
         stats->live_edges = st[3];
         stats->spilled = st[4];
         stats->wave_samples = st[5];
+        stats->pack_samples = st[6];
         stats->device_ms = ms;
         double kms = 0.0;
         for (size_t i = 0; i + 1 < g->kev_used; i += 2) {
@@ -885,7 +925,7 @@ int imin_graph_create_model(int32_t n, int32_t m, const int32_t *row_ptr, const 
         ok(hipMalloc(&g->d_list, 2 * (size_t)n * sizeof(int32_t))) &&
         ok(hipMalloc(&g->d_D, (size_t)n * sizeof(unsigned long long))) &&
         ok(hipMalloc(&g->d_stats, kStats * sizeof(unsigned long long))) &&
-        ok(hipMalloc(&g->d_ctrl, 4 * sizeof(uint32_t))) &&
+        ok(hipMalloc(&g->d_ctrl, imin::kCtrlWords * sizeof(uint32_t))) &&
         ok(hipMalloc(&g->d_sctrl, 2 * sizeof(uint32_t))) &&
         ok(hipMalloc(&g->d_inst, sizeof(imin::InstanceDesc))) &&
         ok(hipMalloc(&g->d_part_d, (size_t)g->parts * sizeof(unsigned long long))) &&
@@ -1209,7 +1249,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         S.nnow = (int32_t)g->masked.size();
         stage.insert(stage.end(), g->masked.begin(), g->masked.end());
     }
-    const int32_t stride = 13 + std::max(max_rounds, 1);
+    const int32_t stride = imin::kGatherB + std::max(max_rounds, 1);
     DeviceBuf<imin::InstanceDesc> d_table;
     DeviceBuf<imin::BatchStage> d_stages;
     DeviceBuf<int32_t> d_stage, d_rounds, d_out;
@@ -1303,8 +1343,8 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         for (int k = 0; k < kStats; ++k)
             st[(size_t)i][k] = (unsigned long long)(uint32_t)o[2 * k] |
                                ((unsigned long long)(uint32_t)o[2 * k + 1] << 32);
-        err[(size_t)i] = (uint32_t)o[12];
-        B[(size_t)i].assign(o + 13, o + 13 + items[(size_t)i].rounds);
+        err[(size_t)i] = (uint32_t)o[imin::kGatherErr];
+        B[(size_t)i].assign(o + imin::kGatherB, o + imin::kGatherB + items[(size_t)i].rounds);
     }
     float total_ms = 0.0f;
     if (!ok(hipEventElapsedTime(&total_ms, g0->ev0, g0->ev1))) return IMIN_EDEVICE;
@@ -1332,6 +1372,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
             o.live_edges = st[(size_t)i][3];
             o.spilled = st[(size_t)i][4];
             o.wave_samples = st[(size_t)i][5];
+            o.pack_samples = st[(size_t)i][6];
             o.device_ms = total_ms;
             o.kernel_ms = kms;
         }

@@ -38,7 +38,8 @@ struct imin_graph {
     unsigned long long *d_D = nullptr;       // n
     unsigned long long *d_stats = nullptr;   // kStats: samples, reached, scanned, live,
                                              // spilled, wave-kernel samples
-    uint32_t *d_ctrl = nullptr;              // 4: next main, next spill, spill count, error
+    uint32_t *d_ctrl = nullptr;              // kCtrlWords: next main, next spill, spill count,
+                                             // error (in batched calls: the instance's words)
     uint32_t *d_sctrl = nullptr;             // 2: wave-kernel work counter, samples it left
     uint32_t *d_sj = nullptr;                // samples the wave kernel left to the large one
     uint32_t sj_cap = 0;
@@ -77,7 +78,8 @@ struct imin_graph {
 namespace imin {
 namespace host {
 
-constexpr int kStats = 6;  // samples, reached, scanned, live, spilled, wave-kernel samples
+constexpr int kStats = 7;  // samples, reached, scanned, live, spilled, wave-level kernel
+                           // samples, packed-kernel samples
 // The per-launch work counter is 32-bit and every workgroup takes one index past the end.
 constexpr uint32_t kMaxTheta = 1u << 31;
 
@@ -124,13 +126,17 @@ int launch_large_on(imin_graph *g, const LargeTarget &t, uint32_t theta, uint64_
 // Device scratch of rounds over many instances at once (batched calls, the server): the
 // wave kernel's hand-over list, the workgroup kernel's slots (maps sized for the largest
 // instance) and its own overflow list, and the control words of one round.
+constexpr int kMultiCtrl = 9;
+
 struct MultiScratch {
     int64_t n = 0, m = 0;      // largest instance it serves
     uint32_t cap = 0;          // samples of the largest round
     Workspace main_ws, big_ws;
-    uint32_t *ctrl = nullptr;  // 7: wave next, wave hand-overs, wave error, main next,
-                               //    big next, overflow count, workgroup error
-    uint32_t *si = nullptr, *sj = nullptr;  // hand-over list: instance, sample
+    uint32_t *ctrl = nullptr;  // kMultiCtrl: wave next, wave hand-overs, wave error, main
+                               // next, big next, overflow count, workgroup error, packed
+                               // next, packed hand-overs
+    uint32_t *pi = nullptr, *pj = nullptr;  // packed kernel's hand-over list: instance, sample
+    uint32_t *si = nullptr, *sj = nullptr;  // wave kernel's hand-over list: instance, sample
     uint32_t *oi = nullptr, *oj = nullptr;  // overflow list: instance, sample
     int32_t inst_cap = 0;                   // instances of the largest round
     unsigned long long *part_d = nullptr;   // inst_cap * kArgParts partial argmax results

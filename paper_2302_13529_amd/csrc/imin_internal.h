@@ -114,13 +114,14 @@ struct InstanceDesc {
     uint32_t *inelig;         // bit v set: v is a seed or blocked (the argmax adds winners)
     const int32_t *seeds;
     unsigned long long *D;    // n decrease counters
-    unsigned long long *stats; // samples, reached, edges scanned, live edges, -, wave samples
+    unsigned long long *stats; // samples, reached, edges scanned, live edges, -, wave-level
+                               // kernel samples, packed-kernel samples
     int32_t *B;               // blocker slots (batched greedy)
     int32_t *x;               // the last round's winner (batched greedy)
     const uint4 *thr_orig;    // thresholds as created (batched set-up restores from them)
-    uint32_t *ctrl;           // 4 control words: the graph's workgroup-kernel counters in
-                              // single calls; in many-instance launches 0 = skip the wave
-                              // kernel, 1 = its hand-overs this round, 3 = error
+    uint32_t *ctrl;           // kCtrlWords control words: the graph's workgroup-kernel
+                              // counters in single calls; in many-instance launches see
+                              // kCtrlSkipWave .. kCtrlPackHanded
     int32_t nseeds;
     int32_t n;
     int32_t nquads;           // quads of thr4
@@ -129,10 +130,23 @@ struct InstanceDesc {
     uint32_t sample_base;
 };
 
+// Control words of an instance in many-instance launches (InstanceDesc::ctrl).
+constexpr int kCtrlWords = 8;
+constexpr int kCtrlSkipWave = 0;    // 1: the wave kernel lists the instance's samples onward
+constexpr int kCtrlWaveHanded = 1;  // samples the wave kernel handed over this round
+constexpr int kCtrlError = 3;       // nonzero: a sample was lost (never expected)
+constexpr int kCtrlSkipPack = 4;    // 1: the packed kernel lists the instance's samples onward
+constexpr int kCtrlPackHanded = 5;  // samples the packed kernel handed over this round
+
 struct SmallArgs {
     const InstanceDesc *inst; // ascending sample_base
     int32_t ninst;
     uint32_t total;           // samples of the launch: sum of the instances' theta
+    // When in_j is non-null the launch works on the list of *in_count samples handed over
+    // by the packed kernel instead: sample idx is sample in_j[idx] of instance in_inst[idx].
+    const uint32_t *in_inst;
+    const uint32_t *in_j;
+    const uint32_t *in_count;
     uint32_t round;           // added to every instance's seed to form the key
     int32_t quad_limit;       // a frontier chunk with more edge quads goes to the large kernel
     int32_t pick_div;         // runs of samples: about remaining / (pick_div * waves)
@@ -147,6 +161,31 @@ struct SmallArgs {
 
 // small.hip
 hipError_t launch_decrease_small(const SmallArgs &a, int grid, hipStream_t stream);
+
+// Packed wave kernel (pack.hip): kPackG samples of one instance share a wavefront, each with
+// capacity kPackV local vertices (root included) and kPackX non-tree live edges, its reached
+// set kept in an LDS hash table of kPackH slots. Independent cascade only.
+constexpr int kPackG = 4;
+constexpr int kPackV = 64;
+constexpr int kPackX = 64;
+constexpr int kPackH = 128;
+constexpr int kPackWaves = 4;
+
+struct PackArgs {
+    const InstanceDesc *inst; // ascending sample_base
+    int32_t ninst;
+    uint32_t total;           // samples of the launch: sum of the instances' theta
+    uint32_t round;           // added to every instance's seed to form the key
+    int32_t quad_limit;       // a frontier vertex with more edge quads is handed over
+    int32_t pick_div;         // runs of samples: about remaining / (pick_div * waves)
+    uint32_t *next;           // work counter
+    uint32_t *out_inst;       // samples handed to the wave kernel: instance, sample index
+    uint32_t *out_j;
+    uint32_t *out_count;
+    uint32_t *error;          // bit 2: dominator iteration did not settle (never expected)
+};
+
+hipError_t launch_decrease_pack(const PackArgs &a, int grid, hipStream_t stream);
 
 // select.hip
 hipError_t launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long value,
@@ -199,6 +238,11 @@ hipError_t launch_batch_gather(const InstanceDesc *inst, const int32_t *rounds, 
 // leave their best (D, vertex) in part_d/part_i (ninst * kArgParts entries); one workgroup
 // per instance then reduces them.
 constexpr int kArgParts = 16;
+// Layout of one instance's record in the batch gather buffer (int32 words): the kGatherStats
+// 64-bit counters as pairs of words, the error word, then the blocker slots.
+constexpr int kGatherStats = 7;
+constexpr int kGatherErr = 2 * kGatherStats;
+constexpr int kGatherB = kGatherErr + 1;
 hipError_t launch_batch_argmax(const InstanceDesc *inst, int32_t ninst, int32_t slot,
                                unsigned long long *part_d, int32_t *part_i, hipStream_t stream);
 

@@ -194,8 +194,12 @@ __global__ void batch_argmax_apply_kernel(const InstanceDesc *inst,
                part_i[blockIdx.x * kArgParts + threadIdx.x]);
     block_best(bd, bi);
     if (threadIdx.x == 0) {
-        if (2ull * I.ctrl[1] > (unsigned long long)I.theta) I.ctrl[0] = 1u;
-        I.ctrl[1] = 0u;
+        if (2ull * I.ctrl[kCtrlWaveHanded] > (unsigned long long)I.theta)
+            I.ctrl[kCtrlSkipWave] = 1u;
+        I.ctrl[kCtrlWaveHanded] = 0u;
+        if (2ull * I.ctrl[kCtrlPackHanded] > (unsigned long long)I.theta)
+            I.ctrl[kCtrlSkipPack] = 1u;
+        I.ctrl[kCtrlPackHanded] = 0u;
         if (bi >= 0) {
             I.inelig[bi >> 5] |= 1u << (bi & 31);
             I.B[slot] = bi;
@@ -214,8 +218,8 @@ __global__ void batch_setup_kernel(const InstanceDesc *inst, const BatchStage *s
     for (int32_t k = threadIdx.x; k < I.nseeds; k += kSelBlock) seeds[k] = stage[S.seeds + k];
     for (int32_t k = threadIdx.x; k < S.words; k += kSelBlock)
         I.inelig[k] = (uint32_t)stage[S.bits + k];
-    if (threadIdx.x < 6) I.stats[threadIdx.x] = 0ull;
-    if (threadIdx.x < 4) I.ctrl[threadIdx.x] = 0u;
+    if (threadIdx.x < kGatherStats) I.stats[threadIdx.x] = 0ull;
+    if (threadIdx.x < kCtrlWords) I.ctrl[threadIdx.x] = 0u;
     uint32_t *thr = reinterpret_cast<uint32_t *>(I.thr4);
     const uint32_t *orig = reinterpret_cast<const uint32_t *>(I.thr_orig);
     if (S.nprev < 0) {
@@ -236,13 +240,13 @@ __global__ void batch_gather_kernel(const InstanceDesc *inst, const int32_t *rou
 {
     const InstanceDesc &I = inst[blockIdx.x];
     int32_t *o = out + (int64_t)blockIdx.x * stride;
-    for (int32_t k = threadIdx.x; k < rounds[blockIdx.x]; k += kSelBlock) o[13 + k] = I.B[k];
-    if (threadIdx.x < 6) {
+    for (int32_t k = threadIdx.x; k < rounds[blockIdx.x]; k += kSelBlock) o[kGatherB + k] = I.B[k];
+    if (threadIdx.x < kGatherStats) {
         const unsigned long long v = I.stats[threadIdx.x];
         o[2 * threadIdx.x] = (int32_t)(uint32_t)v;
         o[2 * threadIdx.x + 1] = (int32_t)(uint32_t)(v >> 32);
     }
-    if (threadIdx.x == 0) o[12] = (int32_t)I.ctrl[3];
+    if (threadIdx.x == 0) o[kGatherErr] = (int32_t)I.ctrl[kCtrlError];
 }
 
 int grid_for(int64_t count)

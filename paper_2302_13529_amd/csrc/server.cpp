@@ -144,7 +144,7 @@ size_t footprint(const imin_graph *g, int32_t nseeds, int32_t b)
     const size_t quads = (size_t)std::max<int64_t>(((int64_t)g->m + 3) / 4, 1);
     return align_up(quads * sizeof(uint4)) + align_up((size_t)g->words * 4) +
            align_up((size_t)std::max(nseeds, 1) * 4) + align_up((size_t)g->n * 8) +
-           align_up(kStats * 8) + align_up(4 * 4) + align_up((size_t)std::max(b, 1) * 4) +
+           align_up(kStats * 8) + align_up(imin::kCtrlWords * 4) + align_up((size_t)std::max(b, 1) * 4) +
            align_up(4);
 }
 
@@ -167,7 +167,7 @@ void carve(imin_server *s, Query &q)
     I.stats = reinterpret_cast<unsigned long long *>(p);
     p += align_up(kStats * 8);
     I.ctrl = reinterpret_cast<uint32_t *>(p);
-    p += align_up(4 * 4);
+    p += align_up(imin::kCtrlWords * 4);
     I.B = reinterpret_cast<int32_t *>(p);
     p += align_up((size_t)std::max(q.b, 1) * 4);
     I.x = reinterpret_cast<int32_t *>(p);
@@ -282,7 +282,7 @@ int retire(imin_server *s)
         s->rounds.push_back(s->active[i].rounds);
         max_rounds = std::max(max_rounds, s->active[i].rounds);
     }
-    const int32_t stride = 13 + max_rounds;
+    const int32_t stride = imin::kGatherB + max_rounds;
     const size_t k = fin.size();
     s->out.assign(k * (size_t)stride, 0);
     int rc = ensure_dev(s->d_out, s->out_cap, s->out.size());
@@ -300,9 +300,9 @@ int retire(imin_server *s)
     for (size_t t = 0; t < k; ++t) {
         Query &q = s->active[fin[t]];
         const int32_t *o = s->out.data() + t * (size_t)stride;
-        if (o[12] != 0) return IMIN_EDEVICE;
+        if (o[imin::kGatherErr] != 0) return IMIN_EDEVICE;
         Result r;
-        r.B.assign(o + 13, o + 13 + q.rounds);
+        r.B.assign(o + imin::kGatherB, o + imin::kGatherB + q.rounds);
         for (int32_t v : r.B)
             if (v < 0) return IMIN_EDEVICE;
         unsigned long long st[kStats];
@@ -315,6 +315,7 @@ int retire(imin_server *s)
         r.stats.live_edges = st[3];
         r.stats.spilled = st[4];
         r.stats.wave_samples = st[5];
+        r.stats.pack_samples = st[6];
         s->done[q.ticket] = std::move(r);
         s->pending.erase(q.ticket);
         s->completed.push_back(q.ticket);

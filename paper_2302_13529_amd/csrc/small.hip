@@ -22,15 +22,16 @@
 // and listed for the large kernel, so results never depend on which path ran.
 #include "imin_internal.h"
 #include "philox.h"
+#include "wave.h"
 
 namespace imin {
 namespace {
 
+using namespace wave;
+
 constexpr int kSW = kSmallWaves;
 constexpr int kSmallBlock = kSW * 64;
 constexpr int kMaxSmallJacobiRounds = 4 * kSmallV;
-constexpr int kSeedSlots = 4;                      // cached seed quads per lane
-constexpr int kSeedCacheQuads = 64 * kSeedSlots;
 constexpr uint32_t kPickMin = 4;                   // samples per work-counter update: a
 constexpr uint32_t kPickMax = 64;                  // share of what remains, within these
 
@@ -47,45 +48,6 @@ struct WaveState {
 struct SmallShared {
     WaveState w[kSW];
 };
-
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-
-// Orders this wave's LDS accesses across lanes (the hardware runs one wave's LDS
-// instructions in order; this keeps the compiler from moving them across the point).
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Inclusive prefix sum across the wave.
-__device__ __forceinline__ int wave_scan(int v)
-{
-    const int lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
-
-__device__ __forceinline__ int quads_of(int e0, int e1)
-{
-    return (e1 > e0) ? (((e1 - 1) >> 2) - (e0 >> 2) + 1) : 0;
-}
-
-__device__ __forceinline__ int pick(uint4 v, int i)
-{
-    return (int)(i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w);
-}
 
 // Per-lane copy of the reached vertex ids: lane l holds local ids l, 64+l, 128+l, 192+l.
 struct Mirror {
@@ -163,95 +125,6 @@ __device__ __forceinline__ void claim_all(WaveState &ws, Mirror &m, SampleCtx &c
         const int s = __builtin_amdgcn_readlane(src, leader);
         if (lane == leader) mask &= mask - 1;
         claim(ws, m, cx, c, s);
-    }
-}
-
-// The current instance's seed level: quad p of the seed frontier sits in lane p % 64,
-// slot p / 64. vmask holds the edges of the quad that belong to the seed's row.
-struct SeedCache {
-    int quad[kSeedSlots];
-    uint4 thr[kSeedSlots];
-    uint4 col[kSeedSlots];
-    uint32_t vmask[kSeedSlots];
-    int total;         // cached quads (uniform); -1 when the seed rows do not fit
-    uint32_t scanned;  // out-edges of the seeds (uniform)
-};
-
-__device__ void build_seed_cache(const InstanceDesc &I, WaveState &ws, SeedCache &sc)
-{
-    const int lane = lane_id();
-    int total = 0;
-    uint32_t scanned = 0;
-    for (int base = 0; base < I.nseeds; base += 64) {
-        const int k = base + lane;
-        int e0 = 0, e1 = 0;
-        if (k < I.nseeds) {
-            const int v = I.seeds[k];
-            e0 = I.row_ptr[v];
-            e1 = I.row_ptr[v + 1];
-        }
-        total += (int)wave_sum((uint32_t)quads_of(e0, e1));
-        scanned += wave_sum((uint32_t)(e1 - e0));
-    }
-    sc.scanned = scanned;
-#pragma unroll
-    for (int s = 0; s < kSeedSlots; ++s) {
-        sc.quad[s] = 0;
-        sc.thr[s] = make_uint4(0, 0, 0, 0);
-        sc.col[s] = make_uint4(0, 0, 0, 0);
-        sc.vmask[s] = 0;
-    }
-    if (total > kSeedCacheQuads) {
-        sc.total = -1;
-        return;
-    }
-    sc.total = total;
-    int off = 0;
-    for (int base = 0; base < I.nseeds; base += 64) {
-        const int k = base + lane;
-        int e0 = 0, e1 = 0;
-        if (k < I.nseeds) {
-            const int v = I.seeds[k];
-            e0 = I.row_ptr[v];
-            e1 = I.row_ptr[v + 1];
-        }
-        const int nq = quads_of(e0, e1);
-        const int incl = wave_scan(nq);
-        const int ctot = __shfl(incl, 63, 64);
-        wave_sync();
-        ws.e0[lane] = e0;
-        ws.e1[lane] = e1;
-        ws.ex[lane] = incl - nq;
-        wave_sync();
-        const int cnt = min(64, I.nseeds - base);
-#pragma unroll
-        for (int s = 0; s < kSeedSlots; ++s) {
-            const int q = lane + 64 * s - off;
-            if (q >= 0 && q < ctot) {
-                int l = 0, h = cnt - 1;
-                while (l < h) {
-                    const int mid = (l + h + 1) >> 1;
-                    if (ws.ex[mid] <= q) l = mid;
-                    else h = mid - 1;
-                }
-                const int f0 = ws.e0[l], f1 = ws.e1[l];
-                const int quad = (f0 >> 2) + (q - ws.ex[l]);
-                const int eb = quad * 4;
-                uint32_t vm = 0;
-                for (int i = 0; i < 4; ++i)
-                    if (eb + i >= f0 && eb + i < f1) vm |= 1u << i;
-                sc.quad[s] = quad;
-                sc.vmask[s] = vm;
-            }
-        }
-        off += ctot;
-    }
-#pragma unroll
-    for (int s = 0; s < kSeedSlots; ++s) {
-        if (sc.vmask[s]) {
-            sc.thr[s] = I.thr4[sc.quad[s]];
-            sc.col[s] = I.col4[sc.quad[s]];
-        }
     }
 }
 
@@ -352,25 +225,6 @@ __device__ __forceinline__ int nca_small(const WaveState &ws, int x, int y, int 
         }
     }
     return x;
-}
-
-// Work counters of the current instance, kept per wave and added to the instance's
-// counters when the wave moves to another instance or ends.
-struct Tally {
-    unsigned long long samples, reached, scanned, live;
-};
-
-__device__ __forceinline__ void flush(const InstanceDesc &I, Tally &t)
-{
-    if (t.samples == 0) return;
-    if (lane_id() == 0) {
-        atomicAdd(&I.stats[0], t.samples);
-        atomicAdd(&I.stats[1], t.reached);
-        atomicAdd(&I.stats[2], t.scanned);
-        atomicAdd(&I.stats[3], t.live);
-        atomicAdd(&I.stats[5], t.samples);
-    }
-    t.samples = t.reached = t.scanned = t.live = 0;
 }
 
 // One sample: BFS, dominators, subtree sizes into D. Returns false when it must be handed
@@ -490,6 +344,9 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
     sc.total = -1;
     Tally tally{0, 0, 0, 0};
     const uint32_t nwaves = gridDim.x * kSW;
+    // list mode: the samples the packed kernel handed over (that launch has finished)
+    const bool listed = a.in_j != nullptr;
+    const uint32_t total = listed ? *a.in_count : a.total;
     for (;;) {
         // Guided self-scheduling: runs of consecutive samples (one instance, one seed cache)
         // that shrink as the launch drains, so the waves finish together.
@@ -497,18 +354,22 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
         if (lane == 0) {
             const uint32_t seen =
                 __hip_atomic_load(a.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (seen < a.total)
+            if (seen < total)
                 want = max(kPickMin,
-                           min(kPickMax, (a.total - seen) / ((uint32_t)a.pick_div * nwaves)));
+                           min(kPickMax, (total - seen) / ((uint32_t)a.pick_div * nwaves)));
             first = atomicAdd(a.next, want);
         }
         first = __builtin_amdgcn_readfirstlane(__shfl(first, 0, 64));
         want = __builtin_amdgcn_readfirstlane(__shfl(want, 0, 64));
-        if (first >= a.total) break;
-        const uint32_t last = min(first + want, a.total);
+        if (first >= total) break;
+        const uint32_t last = min(first + want, total);
         for (uint32_t idx = first; idx < last; ++idx) {
-            if (cur < 0 || idx < cur_lo || idx >= cur_hi) {
-                if (cur >= 0) flush(I, tally);
+            int want_inst = cur;
+            uint32_t j = 0;
+            if (listed) {
+                want_inst = (int)__builtin_amdgcn_readfirstlane(a.in_inst[idx]);
+                j = __builtin_amdgcn_readfirstlane(a.in_j[idx]);
+            } else if (cur < 0 || idx < cur_lo || idx >= cur_hi) {
                 // the last instance whose first sample index is <= idx
                 int lo = 0, hi = a.ninst - 1;
                 while (lo < hi) {
@@ -516,23 +377,31 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
                     if (a.inst[mid].sample_base <= idx) lo = mid;
                     else hi = mid - 1;
                 }
-                cur = __builtin_amdgcn_readfirstlane(lo);
+                want_inst = __builtin_amdgcn_readfirstlane(lo);
+            }
+            if (want_inst != cur) {
+                if (cur >= 0) flush(I, tally);
+                cur = want_inst;
                 I = a.inst[cur];
                 cur_lo = I.sample_base;
                 cur_hi = I.sample_base + I.theta;
                 // Many-instance launches: an instance whose previous round handed most of
-                // its samples over (control word 0, set by the round's argmax) skips this
+                // its samples over (control word set by the round's argmax) skips this
                 // kernel; the results do not depend on which kernel runs a sample.
                 skip = a.spill_inst &&
                        __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                           &I.ctrl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0u;
-                if (kLT || skip) sc.total = -1;  // LT: vertex-keyed choices, no quad cache
-                else build_seed_cache(I, ws, sc);
+                           &I.ctrl[kCtrlSkipWave], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT)) != 0u;
+                // LT: vertex-keyed choices, no quad cache; listed samples come in no
+                // particular instance order, so they read the seed rows from memory
+                if (kLT || skip || listed) sc.total = -1;
+                else build_seed_cache(I, ws.e0, ws.e1, ws.ex, sc);
             }
-            const uint32_t j = idx - cur_lo;
+            if (!listed) j = idx - cur_lo;
             if (skip) {
-                // the rest of the run within this instance, listed at once
-                const uint32_t cnt = min(last, cur_hi) - idx;
+                // the rest of the run within this instance, listed at once (list mode:
+                // this one sample)
+                const uint32_t cnt = listed ? 1u : min(last, cur_hi) - idx;
                 uint32_t pos = 0;
                 if (lane == 0) pos = atomicAdd(a.spill_count, cnt);
                 pos = __builtin_amdgcn_readfirstlane(__shfl(pos, 0, 64));
@@ -547,7 +416,7 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
                 const uint32_t pos = atomicAdd(a.spill_count, 1u);
                 if (a.spill_inst) {
                     a.spill_inst[pos] = (uint32_t)cur;
-                    atomicAdd(&I.ctrl[1], 1u);  // this round's hand-overs of the instance
+                    atomicAdd(&I.ctrl[kCtrlWaveHanded], 1u);  // this round's hand-overs
                 }
                 a.spill_j[pos] = j;
             }

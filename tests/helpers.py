@@ -163,3 +163,54 @@ def spread_moments(n, row_ptr, col, prob, seeds, blocked=None):
         E += w * size
         E2 += w * size * size
     return E, E2
+
+
+_INSTANCE_CACHE = {}
+
+
+def cached(name, make):
+    """A generated workload, kept for the rest of the test session (generation is seeded,
+    so every caller sees the same arrays)."""
+    if name not in _INSTANCE_CACHE:
+        _INSTANCE_CACHE[name] = make()
+    return _INSTANCE_CACHE[name]
+
+
+def read_config_golden(name):
+    """Parse a tests/golden/config_*.txt file written by make_config_goldens.py.
+
+    Returns a dict: 'blockers' -> list, 'calls' -> int, 'stats' -> dict, plus per-item
+    entries keyed (kind, index) -> (blockers, stats) for 'inst' / 'query' lines, and
+    'decrease2048 ...' / 'greedy2 ...' lines under their first word.
+    """
+    out = {}
+
+    def stats_of(words):
+        return {k: int(v) for k, v in (w.split("=") for w in words)}
+
+    for words in read_golden(name):
+        head = words[0]
+        if head in ("inst", "query"):
+            bar = words.index("|")
+            out[(head, int(words[1]))] = ([int(x) for x in words[3:bar]],
+                                          stats_of(words[bar + 1:]))
+        elif head in ("decrease2048", "greedy2"):
+            sub = out.setdefault(head, {})
+            kind = words[1]
+            if kind == "blockers":
+                sub[kind] = [int(x) for x in words[2:]]
+            elif kind == "calls":
+                sub[kind] = int(words[2])
+            elif kind == "stats":
+                sub[kind] = stats_of(words[2:])
+            elif kind == "sha256":
+                sub[kind] = words[2]
+            elif kind == "top":
+                sub[kind] = [tuple(int(y) for y in x.split(":")) for x in words[2:]]
+        elif head == "blockers":
+            out["blockers"] = [int(x) for x in words[1:]]
+        elif head == "calls":
+            out["calls"] = int(words[1])
+        elif head == "stats":
+            out["stats"] = stats_of(words[1:])
+    return out

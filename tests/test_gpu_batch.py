@@ -267,3 +267,54 @@ def test_batch_scratch_kept_across_shapes(gpu, batch16):
             assert list(B) == list(Bp) and st["reached"] == sp["reached"]
     gs.close()
     gb.close()
+
+
+def _star_graph(leaves, p):
+    return H.csr_from_edges(leaves + 1, [(0, i, p) for i in range(1, leaves + 1)])
+
+
+def test_packed_kernel_capacity_edges(gpu):
+    """Batched instances whose samples sit on either side of the packed kernel's limits
+    (63 reached vertices, 64 non-tree live edges, 256 edge quads of one frontier vertex):
+    each result must equal the plain call and the checker, and the samples that fit must
+    have been finished by the packed kernel."""
+    cases = []
+    # certain paths: 63 reached vertices fit exactly, 64 are handed over
+    for n in (63, 64, 65, 66):
+        cases.append((f"path{n}", *_path_graph(n), [0], n - 1 <= 63))
+    # a certain star of 63 leaves fits; one more leaf does not
+    for leaves in (63, 64):
+        cases.append((f"star{leaves}", *_star_graph(leaves, 1.0), [0], leaves <= 63))
+    # 8 certain vertices fully connected: 42 non-tree live edges fit, a 10-clique's 72 do not
+    for k in (8, 10):
+        rp, c, p = H.csr_from_edges(k, [(u, v, 1.0) for u in range(k) for v in range(k) if u != v])
+        cases.append((f"clique{k}", rp, c, p, [0], k <= 8))
+    # a hub of 1100 out-edges behind the seed: its 275 quads exceed the packed quad limit
+    hub = [(0, 1, 1.0)] + [(1, 2 + i, 0.001) for i in range(1100)]
+    cases.append(("hub", *H.csr_from_edges(1102, hub), [0], False))
+    # a mixed instance whose random samples land on both sides of the limits
+    rng = np.random.default_rng(5)
+    cases.append(("mixed", *H.random_graph(rng, 200, 400, probs=(0.5, 0.25, 1.0)), [0, 1], None))
+    graphs = [gpu.Graph(rp, c, p) for _, rp, c, p, _, _ in cases]
+    theta = 96
+    probs = [(g.handle, S, 3, theta, 11 + i) for i, (g, (_, _, _, _, S, _)) in
+             enumerate(zip(graphs, cases))]
+    case("batch over the packed kernel's capacity edges")
+    res = gpu.imin_greedy_batch(probs)
+    for i, ((name, rp, c, p, S, fits), g, (B, st)) in enumerate(zip(cases, graphs, res)):
+        Bo, _, so = orc.greedy(len(rp) - 1, rp, c, p, S, 3, theta, 11 + i, 0)
+        assert list(B) == list(Bo), name
+        for k in ("samples", "reached", "edges_scanned", "live_edges"):
+            assert st[k] == so[k], (name, k)
+        Bp, sp = g.greedy(S, 3, theta, 11 + i, gpu.IMIN_AG)
+        assert list(Bp) == list(B) and sp["reached"] == st["reached"], name
+        case(f"{name}: packed {st['pack_samples']} wave {st['wave_samples']} of {st['samples']}")
+        # the first round decides whether later rounds skip the packed kernel
+        # (a round that hands most samples over sends the instance's later rounds past the
+        # packed kernel)
+        if fits is True:
+            assert st["pack_samples"] == st["samples"], name
+        elif fits is False:
+            assert st["pack_samples"] == 0, name
+    for g in graphs:
+        g.close()

@@ -1,8 +1,8 @@
-"""The batched and served forms at their full input sizes.
+"""The served form and the 2^17-vertex R-MAT graph at their full input sizes, against the
+checker run live (the stored full-budget results are in test_gpu_configs.py).
 
-C3: all 256 Chung-Lu instances in one batched call (theta = 2000, two rounds here), every
-instance against its plain call and a seeded subset against the checker. C5: the
-1M-vertex R-MAT graph with a mix of queries in the server, each against the checker.
+C5: the 1M-vertex R-MAT graph with a mix of queries in the server, each against the
+checker. C2: one Algorithm 2 call at theta = 10^4, every count against the checker.
 """
 import numpy as np
 import pytest
@@ -15,29 +15,6 @@ pytestmark = pytest.mark.gpu
 
 def case(msg):
     print(f"[case] {msg}", flush=True)
-
-
-def test_batch_of_256_full_size(gpu):
-    case("generating the 256 batched instances")
-    insts = gg.batched_instances()
-    graphs = [gpu.Graph(t.row_ptr, t.col, t.prob) for t in insts]
-    probs = [(g.handle, t.seeds, 2, t.theta, t.seed) for g, t in zip(graphs, insts)]
-    case("batched AG over 256 instances, theta 2000, 2 rounds")
-    res = gpu.imin_greedy_batch(probs)
-    assert sum(st["samples"] for _, st in res) == 256 * 2 * 2000
-    rng = np.random.default_rng(256)
-    check = set(int(i) for i in rng.choice(256, size=12, replace=False))
-    for i, (g, t) in enumerate(zip(graphs, insts)):
-        B, st = res[i]
-        Bp, sp = g.greedy(t.seeds, 2, t.theta, t.seed, gpu.IMIN_AG)
-        assert list(B) == list(Bp), i
-        assert st["reached"] == sp["reached"] and st["live_edges"] == sp["live_edges"], i
-        if i in check:
-            case(f"instance {i} (n={t.n}) against the checker")
-            Bo, _, so = orc.greedy(t.n, t.row_ptr, t.col, t.prob, t.seeds, 2, t.theta, t.seed, 0)
-            assert list(B) == list(Bo) and st["reached"] == so["reached"], i
-    for g in graphs:
-        g.close()
 
 
 def test_served_graph_full_size(gpu):

@@ -212,7 +212,7 @@ def test_rmat17_greedy_rounds(gpu, rmat17):
 @pytest.fixture(scope="module")
 def rmat22():
     case("generating rmat22 (4M vertices, 35M edges)")
-    return gg.large_plain()
+    return H.cached("rmat22", gg.large_plain)
 
 
 def test_rmat22_full_size(gpu, rmat22):
