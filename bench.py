@@ -1,14 +1,20 @@
 """Benchmark of the per-round decrease estimate on one MI355X.
 
-Default workload (--workload rmat22): AdvancedGreedy rounds on the 4M-vertex R-MAT graph.
-A step is one greedy round of the hot path: theta = 10,000 live-edge samples, each with
-live-edge decisions, reachability from the merged seed, the dominator tree, subtree sizes
-and the exact accumulation of the decrease counts, followed by the device-side argmax and
-block of the round's winner (Algorithms 2 and 3 of arXiv 2302.13529).
+Headline (default): AdvancedGreedy rounds on the 4M-vertex R-MAT graph. A step is one
+greedy round of the hot path: theta = 10,000 live-edge samples, each with live-edge
+decisions, reachability from the merged seed, the dominator tree, subtree sizes and the
+exact accumulation of the decrease counts, followed by the device-side argmax and block of
+the round's winner (Algorithms 2 and 3 of arXiv 2302.13529).
 
---workload batched: 256 independent Chung-Lu instances (theta = 2,000, b = 20, TR). A step
-is one batched AdvancedGreedy call over all of them (20 rounds); the same instances are
-also run one plain call at a time, and the blockers of both forms must agree exactly.
+The default line also carries two sub-objects:
+* "batched": 256 independent Chung-Lu instances (theta = 2,000, b = 20, TR); a step is one
+  batched AdvancedGreedy call over all of them (20 rounds), against every instance run as a
+  plain call (speed-up, identical blockers);
+* "served": the 2^20-vertex R-MAT graph resident and the 2,000-query mix, saturated
+  (samples/s against plain calls on a prefix), then a prefix under Poisson arrivals (p50 /
+  p99 latency).
+Each carries "verified": its blockers and work counters against the CPU checker's stored
+results at that configuration (tests/golden).
 
 Inputs are seeded synthetic data resident in HBM before the timed region starts. Prints
 one JSON line: samples/s over the timed steps, the roofline figure of the dominant kernel
@@ -33,14 +39,32 @@ HBM_PEAK_GBS = 8000.0
 
 def algorithmic_bytes(stats: dict, n_seeds: int) -> float:
     """8 B per expanded vertex (its row_ptr pair; the seeds and every reached vertex), 8 B
-    per scanned edge (target id + threshold), 8 B per reached vertex (counter update)."""
+    per scanned edge (target id + threshold), 16 B per reached vertex (the read-modify-write
+    of its 64-bit decrease counter)."""
     expanded = stats["samples"] * n_seeds + stats["reached"]
-    return 8.0 * expanded + 8.0 * stats["edges_scanned"] + 8.0 * stats["reached"]
+    return 8.0 * expanded + 8.0 * stats["edges_scanned"] + 16.0 * stats["reached"]
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def golden(name: str) -> dict:
+    """A stored result of the CPU checker at a benchmark configuration (tests/golden), read
+    as text: blocker lists and work counters to compare the GPU's results with."""
+    sys.path.insert(0, ROOT)
+    from tests import helpers
+    path = os.path.join(GOLDEN, name)
+    return helpers.read_config_golden(name) if os.path.exists(path) else {}
+
+
+def _stats4(st: dict) -> dict:
+    return {k: int(st[k]) for k in ("samples", "reached", "edges_scanned", "live_edges")}
 
 
 def traffic_from_profile(path: str, kernel_source: str):
-    """HBM bytes per launch from the committed counter summary, or None when there is none
-    or when the kernel source changed since the counters were taken."""
+    """HBM bytes per launch from the committed counter summary (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE of the same workload, scaled by a copy kernel's calibration), or None when
+    there is none or when the kernel source changed since the counters were taken."""
     if not os.path.exists(path):
         return None
     digest = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
@@ -127,14 +151,17 @@ def cpu_baseline(inst, theta_sample: int, model: str = "ic") -> dict:
                       f"(every {cores}-th sample each), {dt:.1f} s"}
 
 
-def bench_batched(args) -> dict:
+def bench_batched(args, with_cpu: bool) -> dict:
+    """256 Chung-Lu instances: every instance as a plain imin_greedy call, then args.steps
+    batched calls over all of them; blockers compared with each other and with the checker's
+    stored results."""
     import torch
     from paper_2302_13529_amd import binding, graphgen as gg
 
     print("[bench] generating 256 batched instances", file=sys.stderr, flush=True)
     insts = gg.batched_instances()
     cpu = None
-    if not args.no_cpu:
+    if with_cpu:
         # the checker's processes fork before this process touches the GPU
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         cores = cpu_workers()
@@ -148,16 +175,17 @@ def bench_batched(args) -> dict:
     probs = [(g.handle, t.seeds, t.b, t.theta, t.seed) for g, t in zip(graphs, insts)]
     from paper_2302_13529_amd import autotune
     launch = dict(waves_per_cu=args.waves_per_cu, quad_limit=args.quad_limit,
-                  pick_div=args.pick_div)
+                  pick_div=args.pick_div, pack_per_cu=args.pack_per_cu)
     tuned_key = None
     if not any(launch.values()):
         print("[bench] launch shape from the autotuner", file=sys.stderr, flush=True)
         tuned_key, tuned = autotune.tuned_batch_launch(insts, probs, tune_if_missing=args.tune)
         if tuned:
             launch = dict(tuned)
-    launch["graph"] = 1 if args.graph else 0
-    print(f"[bench] warmup: plain and batched, {args.warmup} each", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
+    launch["graph"] = int(args.graph)
+    warm = max(1, args.warmup)
+    print(f"[bench] warmup: plain and batched, {warm} each", file=sys.stderr, flush=True)
+    for _ in range(warm):
         for g, t in zip(graphs, insts):
             g.greedy(t.seeds, t.b, t.theta, t.seed, binding.IMIN_AG)
         binding.imin_greedy_batch(probs, binding.IMIN_AG, launch)
@@ -169,46 +197,50 @@ def bench_batched(args) -> dict:
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
     plain_samples = sum(st["samples"] for _, st in plain)
-    print(f"[bench] batched: {args.steps} calls", file=sys.stderr, flush=True)
+    steps = max(1, args.batched_steps)
+    print(f"[bench] batched: {steps} calls", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         res = binding.imin_greedy_batch(probs, binding.IMIN_AG, launch)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    identical = all(list(a[0]) == list(b[0]) for a, b in zip(plain, res))
+    identical = all(list(a[0]) == list(b[0]) and _stats4(a[1]) == _stats4(b[1])
+                    for a, b in zip(plain, res))
+    want = golden("config_c3.txt")
+    verified = None
+    if want:
+        verified = all([int(x) for x in B] == want[("inst", i)][0] and
+                       _stats4(st) == want[("inst", i)][1] for i, (B, st) in enumerate(res))
     stats = {k: sum(st[k] for _, st in res) for k in
-             ("samples", "reached", "edges_scanned", "live_edges", "wave_samples")}
-    samples = stats["samples"] * args.steps
+             ("samples", "reached", "edges_scanned", "live_edges", "wave_samples",
+              "pack_samples")}
+    samples = stats["samples"] * steps
     kernel_ms = res[0][1]["kernel_ms"]  # the batch's sampling launches, last call
     alg = sum(algorithmic_bytes(st, len(t.seeds)) for (_, st), t in zip(res, insts))
     rounds = max(t.b for t in insts)
     achieved = alg / (kernel_ms / 1e3) / 1e9
     out = {
-        "metric": "live-edge samples/sec incl. dominator decrease",
         "value": samples / dt,
         "unit": "samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
+        "steps": steps,
+        "ms_per_step": dt * 1e3 / steps,
         "config": {"workload": "chunglu_batch256_tr", "instances": len(insts),
                    "theta": insts[0].theta, "b": insts[0].b,
-                   "step": "one batched AdvancedGreedy call over all instances",
-                   "parallelism": "none", "launch": launch, "tuned_key": tuned_key},
+                   "step": "one batched AdvancedGreedy call over all instances (20 rounds)",
+                   "launch": launch, "tuned_key": tuned_key},
         "plain_value": plain_samples / plain_s,
         "speedup_vs_plain": (samples / dt) / (plain_samples / plain_s),
         "identical_to_plain": identical,
+        "verified": {"vs_oracle": verified, "instances": len(insts), "rounds": rounds,
+                     "source": "tests/golden/config_c3.txt"},
+        "pack_share": stats["pack_samples"] / max(1, stats["samples"]),
         "wave_share": stats["wave_samples"] / max(1, stats["samples"]),
-        "teps": stats["edges_scanned"] * args.steps / dt,
+        "teps": stats["edges_scanned"] * steps / dt,
         "reached_per_sample": stats["reached"] / max(1, stats["samples"]),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "decrease_small_kernel",
+                     "kernel": "decrease_pack_kernel with the wave and workgroup kernels of "
+                               "its hand-overs (one round's sampling launches)",
                      "algorithmic_bytes_per_launch": alg / rounds,
                      "avg_launch_ms": kernel_ms / rounds},
     }
@@ -220,17 +252,22 @@ def bench_batched(args) -> dict:
 
 
 def bench_served(args) -> dict:
+    """The 2^20-vertex R-MAT graph resident, the served query mix: a prefix as plain calls,
+    the whole mix saturated (every query submitted at time 0), then a prefix under Poisson
+    arrivals at 0.8x the plain form's query rate for latency."""
     import numpy as np
     import torch
     from paper_2302_13529_amd import binding, graphgen as gg, serve
 
     print("[bench] generating the served graph and queries", file=sys.stderr, flush=True)
     inst = gg.served_graph()
-    queries = gg.served_queries(inst.n)[: args.queries]
+    allq = gg.served_queries(inst.n)
+    queries = allq[: args.queries]
     g = binding.Graph(inst.row_ptr, inst.col, inst.prob)
     budget = int(args.hbm_gib * (1 << 30))
     launch = {k: v for k, v in dict(waves_per_cu=args.waves_per_cu, quad_limit=args.quad_limit,
-                                    pick_div=args.pick_div).items() if v}
+                                    pick_div=args.pick_div,
+                                    pack_per_cu=args.pack_per_cu).items() if v}
     srv = binding.Server(g, hbm_budget=budget, max_active=args.max_active, max_theta=10000,
                          launch=launch or None)
     # plain form: one imin_greedy call per query, on a bounded prefix of the mix
@@ -250,86 +287,60 @@ def bench_served(args) -> dict:
     res, lat_sat, span, steps = serve.run(srv, queries)
     served_samples = sum(st["samples"] for _, st in res)
     identical = all(list(res[i][0]) == list(plain[i][0]) and
-                    res[i][1]["reached"] == plain[i][1]["reached"] for i in range(plain_n))
-    # served, Poisson arrivals at 0.8x the plain form's query rate
+                    _stats4(res[i][1]) == _stats4(plain[i][1]) for i in range(plain_n))
+    want = golden("config_c5.txt")
+    checked = [i for kind, i in want if kind == "query" and i < len(queries)]
+    verified = None
+    if checked:
+        verified = all([int(x) for x in res[i][0]] == want[("query", i)][0] and
+                       _stats4(res[i][1]) == want[("query", i)][1] for i in checked)
+    # served, Poisson arrivals at 0.8x the plain form's query rate, on a prefix of the mix
+    pq = queries[: min(args.poisson_queries, len(queries))]
     rate = 0.8 * plain_qps
-    arrivals = serve.poisson_arrivals(len(queries), rate, seed=7)
-    print(f"[bench] served, Poisson arrivals at {rate:.2f} queries/s", file=sys.stderr,
-          flush=True)
-    res2, lat, span2, steps2 = serve.run(srv, queries, arrivals)
-    identical = identical and all(list(a[0]) == list(b[0]) for a, b in zip(res, res2))
+    arrivals = serve.poisson_arrivals(len(pq), rate, seed=7)
+    print(f"[bench] served, Poisson arrivals at {rate:.2f} queries/s, {len(pq)} queries",
+          file=sys.stderr, flush=True)
+    res2, lat, span2, steps2 = serve.run(srv, pq, arrivals)
+    identical = identical and all(list(a[0]) == list(b[0]) and _stats4(a[1]) == _stats4(b[1])
+                                  for a, b in zip(res, res2))
     srv.close()
     g.close()
-    out = {
-        "metric": "live-edge samples/sec incl. dominator decrease",
+    return {
         "value": served_samples / span,
         "unit": "samples/s",
-        "n_gpus": 1,
         "steps": steps,
-        "warmup": 1,
         "ms_per_step": span * 1e3 / max(steps, 1),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
         "config": {"workload": inst.name, "n": inst.n, "m": inst.m, "queries": len(queries),
                    "step": "one server step: a greedy round of every admitted query",
                    "hbm_budget_gib": args.hbm_gib, "max_active": args.max_active,
-                   "launch": launch,
-                   "parallelism": "none"},
+                   "launch": launch},
         "plain_value": plain_samples / plain_s,
         "plain_queries": plain_n,
         "speedup_vs_plain": (served_samples / span) / (plain_samples / plain_s),
         "identical_to_plain": identical,
+        "verified": {"vs_oracle": verified, "queries": len(checked),
+                     "source": "tests/golden/config_c5.txt"},
         "saturated_makespan_s": span,
+        "queries_per_s_served": len(queries) / span,
+        "queries_per_s_plain": plain_qps,
+        "poisson_queries": len(pq),
         "poisson_rate_qps": rate,
         "latency_p50_s": float(np.percentile(lat, 50)),
         "latency_p99_s": float(np.percentile(lat, 99)),
         "poisson_makespan_s": span2,
-        "queries_per_s_served": len(queries) / span,
-        "queries_per_s_plain": plain_qps,
     }
-    return out
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-samples", type=int, default=256,
-                    help="rmat22: samples the CPU checker times (an eighth of it under LT, whose "
-                         "samples reach about 3x more vertices)")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["rmat22", "batched", "served"], default="rmat22")
-    ap.add_argument("--model", choices=["ic", "lt"], default="ic",
-                    help="rmat22: propagation model (lt: WC weights as linear-threshold weights)")
-    ap.add_argument("--queries", type=int, default=2000, help="served: queries of the mix")
-    ap.add_argument("--plain-queries", type=int, default=40,
-                    help="served: queries timed one plain call at a time")
-    ap.add_argument("--hbm-gib", type=float, default=16.0, help="served: query-state budget")
-    ap.add_argument("--max-active", type=int, default=256, help="served: admitted at once")
-    ap.add_argument("--waves-per-cu", type=int, default=0)
-    ap.add_argument("--quad-limit", type=int, default=0)
-    ap.add_argument("--pick-div", type=int, default=0)
-    ap.add_argument("--graph", action="store_true",
-                    help="batched workload: capture each call's rounds into one HIP graph")
-    ap.add_argument("--tune", action="store_true",
-                    help="batched workload: tune the launch shape if no cached entry exists")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(samples would shard across GPUs with one integer reduction of the counts "
-              "per round; see the design notes)", file=sys.stderr)
-        return 2
-    if args.workload == "batched":
-        print(json.dumps(bench_batched(args)), flush=True)
-        return 0
-    if args.workload == "served":
-        print(json.dumps(bench_served(args)), flush=True)
-        return 0
+def line(value: float, unit: str, steps: int, warmup: int, ms_per_step: float,
+         config: dict) -> dict:
+    return {"metric": "live-edge samples/sec incl. dominator decrease", "value": value,
+            "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u64", "data": "synthetic", "config": config}
 
+
+def bench_headline(args) -> dict:
+    """AdvancedGreedy rounds on the 4M-vertex R-MAT graph (or its LT variant)."""
     import torch
     from paper_2302_13529_amd import binding, graphgen as gg
 
@@ -361,36 +372,90 @@ def main() -> int:
     alg = algorithmic_bytes(st, len(inst.seeds))
     kernel_s = st["kernel_ms"] / 1e3
     achieved = alg / kernel_s / 1e9
-    traffic = traffic_from_profile(
-        os.path.join(ROOT, "profiles", "decrease_kernel_rmat22_pmc.txt"),
-        os.path.join(ROOT, "paper_2302_13529_amd", "csrc", "decrease.hip"))
-    out = {
-        "metric": "live-edge samples/sec incl. dominator decrease",
-        "value": samples / dt,
-        "unit": "samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": inst.name + ("_lt" if args.model == "lt" else ""),
-                   "model": args.model.upper(), "n": inst.n, "m": inst.m, "seeds": len(inst.seeds),
-                   "theta": theta, "step": "one AdvancedGreedy round", "parallelism": "none"},
+    prof = os.path.join("profiles", "decrease_kernel_rmat22_pmc.txt")
+    src = os.path.join("paper_2302_13529_amd", "csrc", "decrease.hip")
+    traffic = traffic_from_profile(os.path.join(ROOT, prof), os.path.join(ROOT, src))
+    out = line(samples / dt, "samples/s", args.steps, args.warmup, dt * 1e3 / args.steps,
+               {"workload": inst.name + ("_lt" if args.model == "lt" else ""),
+                "model": args.model.upper(), "n": inst.n, "m": inst.m,
+                "seeds": len(inst.seeds), "theta": theta, "counter_bits": 64,
+                "step": "one AdvancedGreedy round", "parallelism": "none"})
+    out.update({
         "teps": st["edges_scanned"] / dt,
         "reached_per_sample": st["reached"] / samples,
         "blockers": [int(x) for x in B],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_source": (f"{prof} (rocprofv3 FETCH_SIZE/WRITE_SIZE of this "
+                                        f"kernel source, sha256 match)") if traffic else None,
                      "kernel": "decrease_kernel",
                      "algorithmic_bytes_per_launch": alg / launches,
                      "avg_launch_ms": st["kernel_ms"] / launches},
-    }
+    })
+    want = golden("config_c4.txt").get("greedy2", {})
+    if args.model == "ic" and want.get("blockers"):
+        k = min(len(B), len(want["blockers"]))
+        out["verified"] = {"vs_oracle": [int(x) for x in B[:k]] == want["blockers"][:k],
+                           "rounds": k, "source": "tests/golden/config_c4.txt"}
     if cpu is not None:
         out["cpu_baseline"] = cpu
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-samples", type=int, default=256,
+                    help="rmat22: samples the CPU checker times (an eighth of it under LT, whose "
+                         "samples reach about 3x more vertices)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", choices=["all", "rmat22", "batched", "served"], default="all",
+                    help="all: the rmat22 line with the batched and served forms as sub-objects")
+    ap.add_argument("--model", choices=["ic", "lt"], default="ic",
+                    help="rmat22: propagation model (lt: WC weights as linear-threshold weights)")
+    ap.add_argument("--batched-steps", type=int, default=3, help="batched: timed calls")
+    ap.add_argument("--queries", type=int, default=2000, help="served: queries of the mix")
+    ap.add_argument("--plain-queries", type=int, default=40,
+                    help="served: queries timed one plain call at a time")
+    ap.add_argument("--poisson-queries", type=int, default=300,
+                    help="served: prefix of the mix run under Poisson arrivals for latency")
+    ap.add_argument("--hbm-gib", type=float, default=16.0, help="served: query-state budget")
+    ap.add_argument("--max-active", type=int, default=256, help="served: admitted at once")
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--quad-limit", type=int, default=0)
+    ap.add_argument("--pick-div", type=int, default=0)
+    ap.add_argument("--pack-per-cu", type=int, default=0,
+                    help="batched/served: packed-kernel workgroups per CU (-1: that kernel off)")
+    ap.add_argument("--graph", type=int, choices=[0, 1], default=0,
+                    help="batched workload: 1 captures each call's rounds into a HIP graph")
+    ap.add_argument("--tune", action="store_true",
+                    help="batched workload: tune the launch shape if no cached entry exists")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(samples would shard across GPUs with one integer reduction of the counts "
+              "per round; see the design notes)", file=sys.stderr)
+        return 2
+    if args.workload == "batched":
+        b = bench_batched(args, with_cpu=not args.no_cpu)
+        out = line(b.pop("value"), b.pop("unit"), b.pop("steps"), max(1, args.warmup),
+                   b.pop("ms_per_step"), b.pop("config"))
+        out.update(b)
+        print(json.dumps(out), flush=True)
+        return 0
+    if args.workload == "served":
+        sv = bench_served(args)
+        out = line(sv.pop("value"), sv.pop("unit"), sv.pop("steps"), 1, sv.pop("ms_per_step"),
+                   sv.pop("config"))
+        out.update(sv)
+        print(json.dumps(out), flush=True)
+        return 0
+    out = bench_headline(args)
+    if args.workload == "all":
+        out["batched"] = bench_batched(args, with_cpu=False)
+        out["served"] = bench_served(args)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -184,7 +184,7 @@ IMIN_API int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b,
 IMIN_API int imin_set_launch(imin_graph *g, int32_t slots, int64_t extra_cap);
 
 /*
- * Launch shape of the one-wave-per-sample kernel. Every field 0 means "default"; the values
+ * Launch shape of the wavefront-level kernels. Every field 0 means "default"; the values
  * change speed only, never results.
  *   waves_per_cu  waves launched per compute unit (default 20; the kernel is persistent,
  *                 so waves beyond what fits on a unit start as others finish).
@@ -201,6 +201,10 @@ typedef struct {
     int32_t quad_limit;
     int32_t pick_div;
     int32_t graph;
+    int32_t pack_per_cu;  /* batched calls and the server: workgroups per compute unit of the
+                             kernel that runs several small samples per wavefront (0: the
+                             default, 3; -1: that kernel off, every sample starts in the
+                             one-sample-per-wave kernel) */
 } imin_launch;
 
 /*

@@ -3,9 +3,11 @@
 Launch shapes change speed only, never results (every count is an exact integer sum), so a
 tuner may simply time candidates on the workload and keep the fastest. Two searches:
 
-* ``tune_batch(problems)`` -- the wave-per-sample kernel of the batched greedy call: waves
-  per compute unit, the frontier-chunk quad limit and the run length of the guided sample
-  schedule (``imin_launch``). The probe is the first greedy round of every instance.
+* ``tune_batch(problems)`` -- the wavefront-level kernels of the batched greedy call: waves
+  per compute unit of the one-sample-per-wave kernel, its frontier-chunk quad limit, the run
+  length of the guided sample schedule, and the workgroups per compute unit of the kernel
+  that packs several samples per wave (or that kernel off) (``imin_launch``). The probe is
+  the first greedy round of every instance.
 * ``tune_graph(graph, seeds, theta)`` -- a plain graph: wave kernel on or off, its launch
   shape, and the workgroup kernel's slot count. The probe is one decrease call.
 
@@ -32,6 +34,7 @@ BATCH_GRID = {
     "waves_per_cu": [8, 12, 16, 20, 24, 32],
     "quad_limit": [256, 1024, 2048, 8192],
     "pick_div": [1, 2, 4, 8],
+    "pack_per_cu": [-1, 1, 2, 3, 4],
 }
 GRAPH_GRID = {
     "small": [0, 1],

@@ -41,7 +41,8 @@ class imin_stats(ctypes.Structure):
 
 class imin_launch(ctypes.Structure):
     _fields_ = [("waves_per_cu", ctypes.c_int32), ("quad_limit", ctypes.c_int32),
-                ("pick_div", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("pick_div", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("pack_per_cu", ctypes.c_int32)]
 
 
 def _launch(launch):

@@ -28,7 +28,10 @@ constexpr int32_t kDefaultPackQuadLimit = 256;
 // kPackG samples each per workgroup).
 constexpr int kPackGroupsPerCu = 3;
 
-int pack_grid(int num_cus) { return std::max(1, num_cus) * kPackGroupsPerCu; }
+int pack_grid(int num_cus, const imin_launch &l)
+{
+    return std::max(1, num_cus) * (l.pack_per_cu > 0 ? l.pack_per_cu : kPackGroupsPerCu);
+}
 // In automatic mode the wave kernel is dropped for a graph once fewer than this share of
 // a round's samples finished in it.
 constexpr double kSmallKeepShare = 0.5;
@@ -194,7 +197,7 @@ void small_shape(imin::SmallArgs &s, const imin_launch &l)
 bool launch_ok(const imin_launch *l)
 {
     return !l || (l->waves_per_cu >= 0 && l->quad_limit >= 0 && l->pick_div >= 0 &&
-                  (l->graph == 0 || l->graph == 1));
+                  (l->graph == 0 || l->graph == 1) && l->pack_per_cu >= -1);
 }
 
 int ensure_B(imin_graph *g, int32_t b)
@@ -457,16 +460,16 @@ int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst,
 {
     if (total > ms.cap) return IMIN_ERANGE;
     const bool spill = ms.big_ws.slots > 0;
-    // words 0, 1, 3, 4, 5, 7, 8 restart every round; the error words 2 and 6 accumulate
+    // every word but the error words 2 and 6 restarts every round; those accumulate
     if (!ok(imin::launch_batch_zero(inst, ninst, stream)) ||
         !ok(imin::launch_fill_u32(ms.ctrl, 2, 0, stream)) ||
         !ok(imin::launch_fill_u32(ms.ctrl + 3, 3, 0, stream)) ||
-        !ok(imin::launch_fill_u32(ms.ctrl + 7, 2, 0, stream)))
+        !ok(imin::launch_fill_u32(ms.ctrl + 7, kMultiCtrl - 7, 0, stream)))
         return IMIN_EDEVICE;
     // The smallest samples first, several to a wavefront (independent cascade only: the
     // packed kernel keeps the seed level's edge coins in registers); what outgrows it goes
     // to the one-sample-per-wave kernel through a device-side list.
-    const bool pack = !lt;
+    const bool pack = !lt && shape.pack_per_cu >= 0;
     if (pack) {
         imin::PackArgs p;
         std::memset(&p, 0, sizeof(p));
@@ -476,19 +479,19 @@ int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst,
         p.round = round;
         p.quad_limit = kDefaultPackQuadLimit;
         p.pick_div = shape.pick_div > 0 ? shape.pick_div : kDefaultPickDiv;
-        p.next = ms.ctrl + 7;
+        p.next = ms.ctrl + 8;
         p.out_inst = ms.pi;
         p.out_j = ms.pj;
-        p.out_count = ms.ctrl + 8;
+        p.out_count = ms.ctrl + 7;
         p.error = ms.ctrl + 2;
-        if (!ok(imin::launch_decrease_pack(p, pack_grid(num_cus), stream))) return IMIN_EDEVICE;
+        if (!ok(imin::launch_decrease_pack(p, pack_grid(num_cus, shape), stream))) return IMIN_EDEVICE;
     }
     imin::SmallArgs s;
     std::memset(&s, 0, sizeof(s));
     if (pack) {
         s.in_inst = ms.pi;
         s.in_j = ms.pj;
-        s.in_count = ms.ctrl + 8;
+        s.in_count = ms.ctrl + 7;
     }
     s.inst = inst;
     s.ninst = ninst;
@@ -1173,14 +1176,14 @@ int imin_set_small(imin_graph *g, int32_t enable, const imin_launch *launch)
     if (!g || enable < -1 || enable > 1 || !launch_ok(launch)) return IMIN_EINVAL;
     g->small_mode = enable;
     g->small_auto_off = false;
-    g->small_launch = launch ? *launch : imin_launch{0, 0, 0};
+    g->small_launch = launch ? *launch : imin_launch{0, 0, 0, 0, 0};
     return IMIN_OK;
 }
 
 int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_launch *launch)
 {
     if (!inst || count <= 0 || mode != IMIN_AG || !launch_ok(launch)) return IMIN_EINVAL;
-    const imin_launch shape = launch ? *launch : imin_launch{0, 0, 0};
+    const imin_launch shape = launch ? *launch : imin_launch{0, 0, 0, 0, 0};
     std::vector<BatchItem> items((size_t)count);
     std::vector<imin_graph *> graphs;
     uint64_t theta_sum = 0;

@@ -42,18 +42,21 @@ static_assert(H >= 2 * V, "hash load");
 constexpr int kPackBlock = kPackWaves * 64;
 constexpr int kMaxJacobiRounds = 4 * V;
 constexpr uint32_t kPickMin = 4;
-constexpr uint32_t kPickMax = 64;
+constexpr uint32_t kPickMax = 256;
 
-// LDS state of one sample of a batch.
+// LDS state of one sample of a batch. Local ids (< kPackV) and hash slots (< kPackH) fit a
+// byte, which keeps a sample at about 1.6 KB so that LDS holds four waves per SIMD.
+static_assert(V <= 256 && H <= 256, "byte-sized local ids and hash slots");
 struct PackSample {
-    int key[H];       // hash table of reached vertex ids (-1: empty)
-    int hl[H];        // local id of the vertex in key[], written by the claim's winner
-    int gl[V];        // vertex id of each local id (local 0 is the merged seed: -1)
-    int pa[V];        // parent in the BFS spanning tree
-    int td[V];        // tentative immediate dominator
-    int tn[V];        // next tentative dominator, then subtree sizes
-    int lvl[V + 1];   // first local id of each BFS level
-    int2 extra[X];    // (source local id, hash slot of the target), then the target's local id
+    int key[H];               // hash table of reached vertex ids (-1: empty)
+    int gl[V];                // vertex id of each local id (local 0 is the merged seed: -1)
+    int tn[V];                // next tentative dominator, then subtree sizes
+    uint8_t hl[H];            // local id of the vertex in key[], written by the claim's winner
+    uint8_t pa[V];            // parent in the BFS spanning tree
+    uint8_t td[V];            // tentative immediate dominator
+    uint8_t lvl[V + 4];       // first local id of each BFS level (V + 1 used)
+    uint32_t extra[X];        // source local id | hash slot of the target << 8, then the
+                              // target's local id << 8
     int nV, nX, ovf, pad;
 };
 
@@ -82,9 +85,9 @@ __device__ __forceinline__ void pclaim(PackSample &S, int c, int src)
             const int id = atomicAdd(&S.nV, 1);
             if (id < V) {
                 S.gl[id] = c;
-                S.pa[id] = src;
-                S.td[id] = src;
-                S.hl[h] = id;
+                S.pa[id] = (uint8_t)src;
+                S.td[id] = (uint8_t)src;
+                S.hl[h] = (uint8_t)id;
             } else {
                 S.ovf = 1;
             }
@@ -94,7 +97,7 @@ __device__ __forceinline__ void pclaim(PackSample &S, int c, int src)
             // edges from the merged seed never matter for dominators
             if (src != 0) {
                 const int x = atomicAdd(&S.nX, 1);
-                if (x < X) S.extra[x] = make_int2(src, (int)h);
+                if (x < X) S.extra[x] = (uint32_t)src | (h << 8);
                 else S.ovf = 1;
             }
             return;
@@ -220,7 +223,7 @@ __device__ uint32_t run_batch(const PackArgs &a, const InstanceDesc &I, const Se
         bool any = false;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            if (act[g] && lane == 0) pw.s[g].lvl[L[g] + 1] = fhi[g];
+            if (act[g] && lane == 0) pw.s[g].lvl[L[g] + 1] = (uint8_t)fhi[g];
             pre[g + 1] = pre[g] + (act[g] ? fhi[g] - flo[g] : 0);
             any = any || act[g];
         }
@@ -248,38 +251,49 @@ __device__ uint32_t run_batch(const PackArgs &a, const InstanceDesc &I, const Se
             }
             const int nq = quads_of(e0, e1);
             const int incl = wave_scan(nq);
-            const int total = __shfl(incl, 63, 64);
+            const int total = __builtin_amdgcn_readlane(incl, 63);
             pw.e0[lane] = e0;
             pw.e1[lane] = e1;
             pw.ex[lane] = incl - nq;
             pw.tag[lane] = tag;
             wave_sync();
             const int cnt = min(64, T - base);
-            for (int qb = 0; qb < total; qb += 64) {
-                const int q = qb + lane;
-                uint32_t mask = 0;
-                uint4 col = make_uint4(0, 0, 0, 0);
-                int g = 0, src = 0;
-                if (q < total) {
-                    int l = 0, h = cnt - 1;
-                    while (l < h) {
-                        const int mid = (l + h + 1) >> 1;
-                        if (pw.ex[mid] <= q) l = mid;
-                        else h = mid - 1;
-                    }
-                    const int tg = pw.tag[l];
-                    g = tg >> 16;
-                    src = tg & 0xFFFF;
-                    if (pw.s[g].ovf == 0) {
-                        const int quad = (pw.e0[l] >> 2) + (q - pw.ex[l]);
-                        const uint4 thr = I.thr4[quad];
-                        col = I.col4[quad];
-                        mask = live_mask(quad, j0 + (uint32_t)g, key_lo, key_hi, pw.e0[l],
-                                         pw.e1[l], thr);
+            // two quads per lane in flight: both loads issued before either is used
+            for (int qb = 0; qb < total; qb += 128) {
+                int g[2], src[2];
+                uint32_t mask[2];
+                uint4 col[2];
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    const int q = qb + 64 * h2 + lane;
+                    mask[h2] = 0;
+                    col[h2] = make_uint4(0, 0, 0, 0);
+                    g[h2] = 0;
+                    src[h2] = 0;
+                    if (q < total) {
+                        int l = 0, h = cnt - 1;
+                        while (l < h) {
+                            const int mid = (l + h + 1) >> 1;
+                            if (pw.ex[mid] <= q) l = mid;
+                            else h = mid - 1;
+                        }
+                        const int tg = pw.tag[l];
+                        g[h2] = tg >> 16;
+                        src[h2] = tg & 0xFFFF;
+                        if (pw.s[g[h2]].ovf == 0) {
+                            const int quad = (pw.e0[l] >> 2) + (q - pw.ex[l]);
+                            const uint4 thr = I.thr4[quad];
+                            col[h2] = I.col4[quad];
+                            mask[h2] = live_mask(quad, j0 + (uint32_t)g[h2], key_lo, key_hi,
+                                                 pw.e0[l], pw.e1[l], thr);
+                        }
                     }
                 }
-                add_at(live, g, (uint32_t)__builtin_popcount(mask));
-                claim_mask(pw.s[g], mask, col, src);
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    add_at(live, g[h2], (uint32_t)__builtin_popcount(mask[h2]));
+                    claim_mask(pw.s[g[h2]], mask[h2], col[h2], src[h2]);
+                }
             }
         }
         wave_sync();
@@ -327,9 +341,8 @@ __device__ uint32_t run_batch(const PackArgs &a, const InstanceDesc &I, const Se
         for (int t = 0; t < G; ++t)
             if (g == t) x = kk - xpre[t];
         PackSample &S = pw.s[g];
-        int2 e = S.extra[x];
-        e.y = S.hl[e.y];
-        S.extra[x] = e;
+        const uint32_t e = S.extra[x];
+        S.extra[x] = (e & 0xFFu) | ((uint32_t)S.hl[e >> 8] << 8);
     }
     wave_sync();
 
@@ -353,12 +366,13 @@ __device__ uint32_t run_batch(const PackArgs &a, const InstanceDesc &I, const Se
                 for (int t = 0; t < G; ++t)
                     if (g == t) x = kk - xpre[t];
                 PackSample &S = pw.s[g];
-                const int2 e = S.extra[x];
-                const int tv = S.td[e.y];
-                const int m1 = pnca(S, tv, e.x, bad);
-                const int m2 = pnca(S, tv, S.pa[e.y], bad);
+                const uint32_t e = S.extra[x];
+                const int ex_src = (int)(e & 0xFFu), ex_dst = (int)(e >> 8);
+                const int tv = S.td[ex_dst];
+                const int m1 = pnca(S, tv, ex_src, bad);
+                const int m2 = pnca(S, tv, S.pa[ex_dst], bad);
                 const int mm = min(m1, m2);
-                if (mm < tv) atomicMin(&S.tn[e.y], mm);
+                if (mm < tv) atomicMin(&S.tn[ex_dst], mm);
             }
             wave_sync();
             int changed = 0;
@@ -371,7 +385,7 @@ __device__ uint32_t run_batch(const PackArgs &a, const InstanceDesc &I, const Se
                 PackSample &S = pw.s[g];
                 const int nt = S.tn[v];
                 if (nt != S.td[v]) {
-                    S.td[v] = nt;
+                    S.td[v] = (uint8_t)nt;
                     changed = 1;
                 }
             }
@@ -458,22 +472,36 @@ __global__ __launch_bounds__(kPackBlock) void decrease_pack_kernel(PackArgs a)
     SeedCache sc;
     sc.total = -1;
     Tally tally{0, 0, 0, 0};
-    const uint32_t nwaves = gridDim.x * kPackWaves;
+    // The launch's samples are cut into kPackRegions contiguous regions, one per XCD (the
+    // hardware deals workgroups to the dies in turn), each with its own work counter, so the
+    // instances of a region -- and their graph rows -- stay in that die's L2. A wave takes
+    // runs of consecutive samples from its own region under guided self-scheduling, and from
+    // the other regions once its own is exhausted.
+    const uint32_t home = blockIdx.x % kPackRegions;
+    const uint32_t region_waves = max(1u, gridDim.x * kPackWaves / kPackRegions);
     for (;;) {
-        // Guided self-scheduling of runs of consecutive samples, as in the wave kernel.
-        uint32_t first = 0, want = kPickMin;
+        uint32_t first = 0, last = 0;
         if (lane == 0) {
-            const uint32_t seen =
-                __hip_atomic_load(a.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (seen < a.total)
-                want = max(kPickMin,
-                           min(kPickMax, (a.total - seen) / ((uint32_t)a.pick_div * nwaves)));
-            first = atomicAdd(a.next, want);
+            for (uint32_t t = 0; t < kPackRegions; ++t) {
+                const uint32_t r = (home + t) % kPackRegions;
+                const uint32_t rb = (uint32_t)((uint64_t)a.total * r / kPackRegions);
+                const uint32_t re = (uint32_t)((uint64_t)a.total * (r + 1) / kPackRegions);
+                const uint32_t seen =
+                    __hip_atomic_load(&a.next[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (rb + seen >= re) continue;
+                const uint32_t want = max(
+                    kPickMin, min(kPickMax, (re - rb - seen) / ((uint32_t)a.pick_div * region_waves)));
+                const uint32_t f = atomicAdd(&a.next[r], want);
+                if (rb + f < re) {
+                    first = rb + f;
+                    last = min(first + want, re);
+                    break;
+                }
+            }
         }
         first = __builtin_amdgcn_readfirstlane(__shfl(first, 0, 64));
-        want = __builtin_amdgcn_readfirstlane(__shfl(want, 0, 64));
-        if (first >= a.total) break;
-        const uint32_t last = min(first + want, a.total);
+        last = __builtin_amdgcn_readfirstlane(__shfl(last, 0, 64));
+        if (first >= last) break;
         for (uint32_t idx = first; idx < last;) {
             if (cur < 0 || idx < cur_lo || idx >= cur_hi) {
                 if (cur >= 0) flush(I, tally, true);

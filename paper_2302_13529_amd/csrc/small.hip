@@ -170,7 +170,7 @@ __device__ void expand_small(const InstanceDesc &I, WaveState &ws, Mirror &m, Sa
         const int nq = quads_of(e0, e1);
         cx.scanned += (uint32_t)(e1 - e0);
         const int incl = wave_scan(nq);
-        const int total = __shfl(incl, 63, 64);
+        const int total = __builtin_amdgcn_readlane(incl, 63);
         if (total > quad_limit) {  // a heavy frontier: the large kernel does this better
             cx.ovf = 1;
             return;

@@ -21,23 +21,25 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+// Inclusive prefix sum across the wave with data-parallel-primitive (DPP) lane moves, which
+// stay in the vector unit: a log-step scan inside each row of 16 lanes (row_shr 1, 2, 4, 8),
+// then the totals of rows 0 and 2 broadcast into rows 1 and 3 (row_bcast:15) and the total of
+// rows 0-1 into rows 2 and 3 (row_bcast:31). Lanes without a source add the old value 0.
+__device__ __forceinline__ int wave_scan(int v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
     return v;
 }
 
-// Inclusive prefix sum across the wave.
-__device__ __forceinline__ int wave_scan(int v)
+// Sum over the wave, the same value in every lane (scalar register).
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
-    return v;
+    return (uint32_t)__builtin_amdgcn_readlane(wave_scan((int)v), 63);
 }
 
 __device__ __forceinline__ int quads_of(int e0, int e1)
@@ -103,7 +105,7 @@ __device__ inline void build_seed_cache(const InstanceDesc &I, int *e0s, int *e1
         }
         const int nq = quads_of(e0, e1);
         const int incl = wave_scan(nq);
-        const int ctot = __shfl(incl, 63, 64);
+        const int ctot = __builtin_amdgcn_readlane(incl, 63);
         wave_sync();
         e0s[lane] = e0;
         e1s[lane] = e1;
