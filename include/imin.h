@@ -203,7 +203,7 @@ typedef struct {
     int32_t graph;
     int32_t pack_per_cu;  /* batched calls and the server: workgroups per compute unit of the
                              kernel that runs several small samples per wavefront (0: the
-                             default, 3; -1: that kernel off, every sample starts in the
+                             default, 2; -1: that kernel off, every sample starts in the
                              one-sample-per-wave kernel) */
 } imin_launch;
 

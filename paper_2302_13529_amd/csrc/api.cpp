@@ -26,7 +26,7 @@ constexpr int32_t kDefaultPickDiv = 4;
 constexpr int32_t kDefaultPackQuadLimit = 256;
 // Packed kernel workgroups per compute unit: as many as its LDS allows (kPackWaves waves of
 // kPackG samples each per workgroup).
-constexpr int kPackGroupsPerCu = 3;
+constexpr int kPackGroupsPerCu = 2;
 
 int pack_grid(int num_cus, const imin_launch &l)
 {

@@ -126,7 +126,7 @@ int launch_large_on(imin_graph *g, const LargeTarget &t, uint32_t theta, uint64_
 // Device scratch of rounds over many instances at once (batched calls, the server): the
 // wave kernel's hand-over list, the workgroup kernel's slots (maps sized for the largest
 // instance) and its own overflow list, and the control words of one round.
-constexpr int kMultiCtrl = 8 + (int)imin::kPackRegions;
+constexpr int kMultiCtrl = 9;
 
 struct MultiScratch {
     int64_t n = 0, m = 0;      // largest instance it serves
@@ -134,7 +134,7 @@ struct MultiScratch {
     Workspace main_ws, big_ws;
     uint32_t *ctrl = nullptr;  // kMultiCtrl: wave next, wave hand-overs, wave error, main
                                // next, big next, overflow count, workgroup error, packed
-                               // hand-overs, then the packed kernel's region counters
+                               // hand-overs, packed next
     uint32_t *pi = nullptr, *pj = nullptr;  // packed kernel's hand-over list: instance, sample
     uint32_t *si = nullptr, *sj = nullptr;  // wave kernel's hand-over list: instance, sample
     uint32_t *oi = nullptr, *oj = nullptr;  // overflow list: instance, sample

@@ -170,8 +170,6 @@ constexpr int kPackV = 64;
 constexpr int kPackX = 64;
 constexpr int kPackH = 128;
 constexpr int kPackWaves = 4;
-// Regions of a packed launch's samples, one per XCD of the MI355X (each die has its own L2).
-constexpr uint32_t kPackRegions = 8;
 
 struct PackArgs {
     const InstanceDesc *inst; // ascending sample_base
@@ -180,7 +178,7 @@ struct PackArgs {
     uint32_t round;           // added to every instance's seed to form the key
     int32_t quad_limit;       // a frontier vertex with more edge quads is handed over
     int32_t pick_div;         // runs of samples: about remaining / (pick_div * waves)
-    uint32_t *next;           // kPackRegions work counters, one per region of the samples
+    uint32_t *next;           // work counter
     uint32_t *out_inst;       // samples handed to the wave kernel: instance, sample index
     uint32_t *out_j;
     uint32_t *out_count;

@@ -41,8 +41,8 @@ static_assert((1 << kHashBits) == H, "hash size");
 static_assert(H >= 2 * V, "hash load");
 constexpr int kPackBlock = kPackWaves * 64;
 constexpr int kMaxJacobiRounds = 4 * V;
-constexpr uint32_t kPickMin = 4;
-constexpr uint32_t kPickMax = 256;
+constexpr uint32_t kPickMin = 8;
+constexpr uint32_t kPickMax = 64;
 
 // LDS state of one sample of a batch. Local ids (< kPackV) and hash slots (< kPackH) fit a
 // byte, which keeps a sample at about 1.6 KB so that LDS holds four waves per SIMD.
@@ -472,32 +472,21 @@ __global__ __launch_bounds__(kPackBlock) void decrease_pack_kernel(PackArgs a)
     SeedCache sc;
     sc.total = -1;
     Tally tally{0, 0, 0, 0};
-    // The launch's samples are cut into kPackRegions contiguous regions, one per XCD (the
-    // hardware deals workgroups to the dies in turn), each with its own work counter, so the
-    // instances of a region -- and their graph rows -- stay in that die's L2. A wave takes
-    // runs of consecutive samples from its own region under guided self-scheduling, and from
-    // the other regions once its own is exhausted.
-    const uint32_t home = blockIdx.x % kPackRegions;
-    const uint32_t region_waves = max(1u, gridDim.x * kPackWaves / kPackRegions);
+    // Guided self-scheduling of runs of consecutive samples (one instance, one seed cache)
+    // that shrink as the launch drains. The remaining count is estimated from the counter
+    // value the wave's previous claim returned, so a claim costs one device-scope atomic.
+    const uint32_t nwaves = gridDim.x * kPackWaves;
+    uint32_t seen = 0;
     for (;;) {
         uint32_t first = 0, last = 0;
         if (lane == 0) {
-            for (uint32_t t = 0; t < kPackRegions; ++t) {
-                const uint32_t r = (home + t) % kPackRegions;
-                const uint32_t rb = (uint32_t)((uint64_t)a.total * r / kPackRegions);
-                const uint32_t re = (uint32_t)((uint64_t)a.total * (r + 1) / kPackRegions);
-                const uint32_t seen =
-                    __hip_atomic_load(&a.next[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (rb + seen >= re) continue;
-                const uint32_t want = max(
-                    kPickMin, min(kPickMax, (re - rb - seen) / ((uint32_t)a.pick_div * region_waves)));
-                const uint32_t f = atomicAdd(&a.next[r], want);
-                if (rb + f < re) {
-                    first = rb + f;
-                    last = min(first + want, re);
-                    break;
-                }
-            }
+            const uint32_t want =
+                seen < a.total
+                    ? max(kPickMin, min(kPickMax, (a.total - seen) / ((uint32_t)a.pick_div * nwaves)))
+                    : kPickMin;
+            first = atomicAdd(a.next, want);
+            seen = first + want;
+            last = min(first + want, a.total);
         }
         first = __builtin_amdgcn_readfirstlane(__shfl(first, 0, 64));
         last = __builtin_amdgcn_readfirstlane(__shfl(last, 0, 64));
