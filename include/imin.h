@@ -321,6 +321,34 @@ IMIN_API int imin_server_completed(imin_server *s, uint64_t *tickets, int32_t ca
 IMIN_API int imin_server_result(imin_server *s, uint64_t ticket, int32_t *blockers, int32_t cap,
                                 int32_t *n_blockers, imin_stats *stats);
 
+/*
+ * imin_decrease_noalloc -- imin_decrease for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * It computes the same counts and work counters as imin_decrease with the same arguments,
+ * and calls no hipMalloc, hipFree or other allocating routine: every scratch buffer of the
+ * call (seed staging, blocked marks, hand-over and overflow lists, the per-slot maps,
+ * records and extra-edge lists of the workgroup kernel, its large-capacity spill slots) is
+ * carved from one static device array of IMIN_NOALLOC_SCRATCH_BYTES per GPU, which each GPU
+ * the library runs on holds until the process ends.
+ *   g, S, nS, blocked, theta, seed   as for imin_decrease.
+ *   d_counts  DEVICE pointer to uint64[n] on g's device, owned by the caller; receives D
+ *             (written only by the kernels; its contents are undefined if the call fails).
+ *   stats     optional host struct, as for imin_decrease (device_ms and kernel_ms are both
+ *             the whole call).
+ * Limits: the graph's scratch must fit the array -- per workgroup slot about 24 * (n + 1)
+ * bytes plus 2 * n, plus two large-capacity slots of about 24 * n + 8 * m bytes when a slot's
+ * extra-edge list cannot hold m edges, plus 8 * theta + 9 * n bytes of lists and marks --
+ * else IMIN_ERANGE (for example a 2^17-vertex, 10^6-edge graph fits; a 2^22-vertex one does
+ * not). Fewer slots than imin_decrease uses may fit, which costs speed, never results.
+ * Every call on one GPU shares that GPU's array, so calls that overlap on one GPU race;
+ * the call clears what must start at zero and leaves the graph's thresholds as created.
+ * Errors: IMIN_EINVAL (as imin_decrease, or d_counts NULL), IMIN_ERANGE, IMIN_EDEVICE.
+ */
+#define IMIN_NOALLOC_SCRATCH_BYTES (256u << 20)
+IMIN_API int imin_decrease_noalloc(imin_graph *g, const int32_t *S, int32_t nS,
+                                   const uint8_t *blocked, uint32_t theta, uint64_t seed,
+                                   uint64_t *d_counts, imin_stats *stats);
+
 /* Human-readable text of a status code (static storage). */
 IMIN_API const char *imin_strerror(int status);
 

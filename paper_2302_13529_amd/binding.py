@@ -124,6 +124,9 @@ def load() -> ctypes.CDLL:
     lib.imin_server_result.argtypes = [P, ctypes.c_uint64, P, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(imin_stats)]
     lib.imin_server_result.restype = ctypes.c_int
+    lib.imin_decrease_noalloc.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_uint32,
+                                          ctypes.c_uint64, P, ctypes.POINTER(imin_stats)]
+    lib.imin_decrease_noalloc.restype = ctypes.c_int
     lib.imin_strerror.argtypes = [ctypes.c_int]
     lib.imin_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -180,6 +183,23 @@ def imin_decrease(handle: int, n: int, seeds, blocked, theta: int, seed: int):
     if rc != IMIN_OK:
         raise IminError("imin_decrease", rc)
     return D, st.as_dict()
+
+
+def imin_decrease_noalloc(handle: int, n: int, seeds, blocked, theta: int, seed: int,
+                          d_counts: int):
+    """Algorithm 2 into the caller's device buffer of n uint64 (address d_counts), through
+    the entry point that allocates nothing; returns the stats dict."""
+    S = np.ascontiguousarray(seeds, dtype=np.int32)
+    blk = None if blocked is None else np.ascontiguousarray(blocked, dtype=np.uint8)
+    if blk is not None and blk.shape[0] != n:
+        raise ValueError("blocked must have n entries")
+    st = imin_stats()
+    rc = load().imin_decrease_noalloc(ctypes.c_void_p(handle), _p(S), S.shape[0], _p(blk),
+                                      int(theta), int(seed) & (2**64 - 1),
+                                      ctypes.c_void_p(int(d_counts)), ctypes.byref(st))
+    if rc != IMIN_OK:
+        raise IminError("imin_decrease_noalloc", rc)
+    return st.as_dict()
 
 
 def imin_spread(handle: int, n: int, seeds, blocked, theta: int, seed: int):

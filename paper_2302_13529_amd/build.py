@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libimin.so")
-SOURCES = ["decrease.hip", "small.hip", "pack.hip", "select.hip", "api.cpp", "server.cpp"]
+SOURCES = ["decrease.hip", "small.hip", "pack.hip", "select.hip", "api.cpp", "server.cpp",
+           "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
