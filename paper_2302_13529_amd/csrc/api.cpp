@@ -62,7 +62,7 @@ void free_ws(Workspace &ws)
 
 size_t slot_bytes(int64_t n, int64_t lcap, int64_t xcap, bool rng = false)
 {
-    return (size_t)n * sizeof(uint32_t) + (size_t)lcap * sizeof(imin::LocalVtx) +
+    return (size_t)n * sizeof(unsigned long long) + (size_t)lcap * sizeof(imin::LocalVtx) +
            (size_t)(lcap + 1) * sizeof(int32_t) + (size_t)xcap * sizeof(int2) + sizeof(uint32_t) +
            (rng ? (size_t)lcap * sizeof(int2) : 0);
 }
@@ -79,7 +79,7 @@ int alloc_ws(Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap
     while (lbits < 32 && (int64_t(1) << lbits) <= lcap) ++lbits;
     if (lbits > 31) return IMIN_ERANGE;
     const size_t S = (size_t)slots;
-    bool good = ok(hipMalloc(&ws.map, S * (size_t)n * sizeof(uint32_t))) &&
+    bool good = ok(hipMalloc(&ws.map, S * (size_t)n * sizeof(unsigned long long))) &&
                 ok(hipMalloc(&ws.loc, S * (size_t)lcap * sizeof(imin::LocalVtx))) &&
                 ok(hipMalloc(&ws.lvl, S * (size_t)(lcap + 1) * sizeof(int32_t))) &&
                 ok(hipMalloc(&ws.extra, S * (size_t)std::max<int64_t>(xcap, 1) * sizeof(int2))) &&
@@ -90,7 +90,7 @@ int alloc_ws(Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap
         (void)hipGetLastError();
         return IMIN_ENOMEM;
     }
-    if (!ok(hipMemsetAsync(ws.map, 0, S * (size_t)n * sizeof(uint32_t), stream)) ||
+    if (!ok(hipMemsetAsync(ws.map, 0, S * (size_t)n * sizeof(unsigned long long), stream)) ||
         !ok(hipMemsetAsync(ws.epoch, 0, S * sizeof(uint32_t), stream))) {
         free_ws(ws);
         return IMIN_EDEVICE;
@@ -359,17 +359,22 @@ int launch_large_on(imin_graph *g, const LargeTarget &t, uint32_t theta, uint64_
     a.error = t.ctrl + 3;
     a.spill_ok = spill ? 1 : 0;
     a.reach_only = reach_only ? 1 : 0;
+    a.count_reach = reach_only ? 0 : 1;
     a.ws = *t.main_ws;
     a.ws.slots = (int32_t)std::min<uint32_t>((uint32_t)t.main_ws->slots, theta);
+    const int32_t used = a.ws.slots;
     if (!ok(imin::launch_decrease(a, g->stream))) return IMIN_EDEVICE;
     if (spill) {
         a.sample_list = t.ovf;
         a.sample_count = t.ctrl + 2;
         a.next = t.ctrl + 1;
         a.spill_ok = 0;
+        a.count_reach = 0;
         a.ws = *t.big_ws;
         if (!ok(imin::launch_decrease(a, g->stream))) return IMIN_EDEVICE;
     }
+    if (!reach_only && !ok(imin::launch_flush_counts(*t.main_ws, used, t.D, g->stream)))
+        return IMIN_EDEVICE;
     return IMIN_OK;
 }
 

@@ -33,6 +33,8 @@
 #include "imin_internal.h"
 #include "philox.h"
 
+#include <algorithm>
+
 namespace imin {
 namespace {
 
@@ -77,7 +79,7 @@ struct Call {
 
 struct SlotView {
     int2 *rng;  // many-instance launches: row range of each local vertex
-    uint32_t *map;
+    unsigned long long *map;
     LocalVtx *loc;
     int32_t *lvl;
     int2 *extra;
@@ -114,14 +116,18 @@ __device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv,
 {
     int2 r = make_int2(0, 0);
     if (kRng) r = make_int2(row_ptr[w], row_ptr[w + 1]);
-    const uint32_t old =
-        __hip_atomic_fetch_max(&sv.map[w], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (old < tag) {
+    const unsigned long long tag64 = (unsigned long long)tag << 32;
+    const unsigned long long old = __hip_atomic_fetch_max(&sv.map[w], tag64, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (old < tag64) {
         const int id = atomicAdd(&sh.tail, 1);
         if (id < a.ws.lcap) {
-            // a later max with tag leaves this larger value in place
-            __hip_atomic_store(&sv.map[w], tag | (uint32_t)(id + 1), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
+            // a later max with tag64 leaves this larger value in place; the count word
+            // (low) gains this sample's reach
+            const uint32_t cnt = (uint32_t)old + (a.count_reach ? 1u : 0u);
+            __hip_atomic_store(&sv.map[w],
+                               ((unsigned long long)(tag | (uint32_t)(id + 1)) << 32) | cnt,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             LocalVtx rec;
             rec.glob = w;
             rec.par0 = src;
@@ -130,6 +136,9 @@ __device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv,
             sv.loc[id] = rec;
             if (kRng) sv.rng[id] = r;
         } else {
+            // keep the slot's count (the sample is abandoned and re-run elsewhere)
+            __hip_atomic_store(&sv.map[w], tag64 | (uint32_t)old, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
             sh.ovf = 1;
         }
     } else if (src != 0 && !a.reach_only) {
@@ -312,7 +321,8 @@ void decrease_kernel(DecreaseArgs a)
         if (epoch >= emax) {
             // every epoch value is used up: clear this slot's map (the barrier below orders
             // the stores before the sample's claims) and start again from epoch 1
-            for (int64_t i = tid; i < a.ws.n; i += B) sv.map[i] = 0u;
+            for (int64_t i = tid; i < a.ws.n; i += B)
+                reinterpret_cast<uint32_t *>(&sv.map[i])[1] = 0u;
             epoch = 0;
         }
         ++epoch;
@@ -349,6 +359,13 @@ void decrease_kernel(DecreaseArgs a)
             __syncthreads();
         }
         if (sh.ovf) {
+            // the sample is re-run elsewhere: take back the reach counts of its claims
+            if (a.count_reach) {
+                const int nv = min(sh.tail, (int)a.ws.lcap);
+                for (int i = 1 + tid; i < nv; i += B)
+                    __hip_atomic_fetch_sub(reinterpret_cast<uint32_t *>(&sv.map[sv.loc[i].glob]),
+                                           1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
             if (tid == 0) {
                 if (a.spill_ok) {
                     const uint32_t pos = atomicAdd(a.ovf_count, 1u);
@@ -372,8 +389,8 @@ void decrease_kernel(DecreaseArgs a)
         const uint32_t lmask = (1u << a.ws.lbits) - 1u;
         for (int x = tid; x < nX; x += B) {
             int2 e = sv.extra[x];
-            e.y = (int)(__hip_atomic_load(&sv.map[e.y], __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT) & lmask) - 1;
+            e.y = (int)((uint32_t)(__hip_atomic_load(&sv.map[e.y], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT) >> 32) & lmask) - 1;
             sv.extra[x] = e;
         }
         __syncthreads();
@@ -452,7 +469,9 @@ void decrease_kernel(DecreaseArgs a)
                 if (r.tdom != 0)
                     __hip_atomic_fetch_add(&sv.loc[r.tdom].csz, r.csz, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
-                atomicAdd(&c.D[r.glob], (unsigned long long)r.csz);
+                // with reach counts in the map, a leaf of the dominator tree adds nothing here
+                const int add = a.count_reach ? r.csz - 1 : r.csz;
+                if (add > 0) atomicAdd(&c.D[r.glob], (unsigned long long)add);
             }
             __syncthreads();
         }
@@ -466,7 +485,49 @@ void decrease_kernel(DecreaseArgs a)
     if (tid == 0) a.ws.epoch[slot] = epoch;
 }
 
+// D[v] += the reach counts of v in a group of kFlushSlots slots (blockIdx.y), which go back
+// to 0. A thread owns v within its group and has all the group's loads in flight at once;
+// for each slot the threads of a wave read consecutive entries.
+constexpr int kFlushSlots = 16;
+
+__global__ void flush_counts_kernel(unsigned long long *map, int32_t slots, int64_t n,
+                                    unsigned long long *D)
+{
+    const int32_t s0 = blockIdx.y * kFlushSlots;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t k[kFlushSlots];
+#pragma unroll
+        for (int i = 0; i < kFlushSlots; ++i)
+            k[i] = s0 + i < slots
+                       ? reinterpret_cast<const uint32_t *>(
+                             &map[(size_t)(s0 + i) * (size_t)n + (size_t)v])[0]
+                       : 0u;
+        unsigned long long sum = 0;
+#pragma unroll
+        for (int i = 0; i < kFlushSlots; ++i) {
+            if (k[i]) {
+                sum += k[i];
+                reinterpret_cast<uint32_t *>(&map[(size_t)(s0 + i) * (size_t)n + (size_t)v])[0] =
+                    0u;
+            }
+        }
+        if (sum) atomicAdd(&D[v], sum);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_flush_counts(const Workspace &ws, int32_t slots, unsigned long long *D,
+                               hipStream_t stream)
+{
+    if (slots <= 0 || ws.n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>(4096, (ws.n + 255) / 256);
+    const int groups = (slots + kFlushSlots - 1) / kFlushSlots;
+    hipLaunchKernelGGL(flush_counts_kernel, dim3((unsigned)blocks, (unsigned)groups), dim3(256), 0,
+                       stream, ws.map, slots, ws.n, D);
+    return hipGetLastError();
+}
 
 hipError_t launch_decrease(const DecreaseArgs &a, hipStream_t stream)
 {

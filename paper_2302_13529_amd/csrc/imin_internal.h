@@ -21,13 +21,19 @@ constexpr int kMultiSlotsPerCu = 2048 / kMultiBlock;
 // the rule that a live edge never activates a seed again or a blocked vertex (Definition 2;
 // each edge's coin is independent of the others). The kernels therefore never test it.
 
-// Per slot and vertex, one 32-bit map entry: (epoch << lbits) | (lid + 1), the epoch of the
-// sample that last reached the vertex above its local id in that sample. A sample with
-// epoch t claims a vertex by an atomic max with t << lbits: the entry was below that value
-// exactly when the vertex was not yet reached in this sample. A lid field of 0 means
-// "claimed, local id not yet written"; the claimer writes the id right after. When a slot's
-// epoch reaches the largest value the upper bits hold, the slot clears its own map and
-// starts again from epoch 1.
+// Per slot and vertex, one 64-bit map entry. Its high word is (epoch << lbits) | (lid + 1),
+// the epoch of the sample that last reached the vertex above its local id in that sample;
+// its low word counts the launch's samples in this slot that reached the vertex. A sample
+// with epoch t claims a vertex by a 64-bit atomic max with (t << lbits) << 32: the entry was
+// below that value exactly when the vertex was not yet reached in this sample, and the
+// atomic returns the old count. The claimer then stores its local id and the count plus one
+// in one store (a later max by the same sample leaves the larger value in place); a lid
+// field of 0 means "claimed, local id not yet written". Counting each reached vertex's 1 in
+// its decrease count this way costs no memory access beyond the claim, and only subtree
+// sizes above 1 go to the device-wide counters (single-problem launches; many-instance
+// launches keep the count at 0 and add every size to D). When a slot's epoch reaches the
+// largest value the high word holds, the slot clears its high words and starts again from
+// epoch 1.
 
 // Per slot and local vertex (local id 0 is the merged seed): the vertex id, the parent in
 // the BFS spanning tree, the tentative immediate dominator and the subtree size. One
@@ -46,7 +52,7 @@ struct Workspace {
     int64_t n = 0;             // map entries per slot (vertex ids below n)
     int64_t lcap = 0;          // local vertices per sample (root included)
     int64_t xcap = 0;          // non-tree live edges per sample
-    uint32_t *map = nullptr;   // slots * n
+    unsigned long long *map = nullptr;  // slots * n
     int32_t lbits = 0;         // bits of the local-id field: lcap < 2^lbits, lbits <= 31
     LocalVtx *loc = nullptr;   // slots * lcap
     int32_t *lvl = nullptr;    // slots * (lcap + 1): first local id of each BFS level
@@ -82,6 +88,8 @@ struct DecreaseArgs {
     uint32_t *error;         // set when a sample overflows with spill_ok == 0
     int32_t spill_ok;
     int32_t reach_only;      // count reached vertices only (spread estimates)
+    int32_t count_reach;     // add each reached vertex's 1 into its slot's map entry (the
+                             // caller folds them into D with launch_flush_counts)
     Workspace ws;            // slot maps of `n` entries
     // Many-instance launches (inst non-null): sample idx is sample sample_list[idx] of
     // instance inst[sample_inst[idx]] with key seed + round; overflowing samples are
@@ -94,6 +102,9 @@ struct DecreaseArgs {
 
 // decrease.hip
 hipError_t launch_decrease(const DecreaseArgs &a, hipStream_t stream);
+// D[v] += the reach counts of v in the first `slots` slots of ws, which are cleared.
+hipError_t launch_flush_counts(const Workspace &ws, int32_t slots, unsigned long long *D,
+                               hipStream_t stream);
 
 // Wave-per-sample kernel (small.hip): per-sample capacity in local vertices (root
 // included) and in non-tree live edges, and waves per workgroup.

@@ -104,7 +104,7 @@ bool carve_ws(Carve &c, imin::Workspace &ws, int64_t n, int32_t slots, int64_t l
     while (lbits < 32 && (int64_t(1) << lbits) <= lcap) ++lbits;
     if (lbits > 31) return false;
     const size_t S = (size_t)slots;
-    ws.map = c.take<uint32_t>(S * (size_t)n);
+    ws.map = c.take<unsigned long long>(S * (size_t)n);
     ws.loc = c.take<imin::LocalVtx>(S * (size_t)lcap);
     ws.lvl = c.take<int32_t>(S * (size_t)(lcap + 1));
     ws.extra = c.take<int2>(S * (size_t)std::max<int64_t>(xcap, 1));
@@ -210,7 +210,8 @@ int imin_decrease_noalloc(imin_graph *g, const int32_t *S, int32_t nS, const uin
     const imin::Workspace *wss[2] = {&main_ws, &big_ws};
     for (const imin::Workspace *w : wss) {
         if (w->slots <= 0) continue;
-        if (!ok(imin::launch_fill_u32(w->map, (int64_t)w->slots * w->n, 0u, st)) ||
+        if (!ok(imin::launch_fill_u32(reinterpret_cast<uint32_t *>(w->map),
+                                      2 * (int64_t)w->slots * w->n, 0u, st)) ||
             !ok(imin::launch_fill_u32(w->epoch, w->slots, 0u, st)))
             return IMIN_EDEVICE;
     }
