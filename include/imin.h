@@ -241,15 +241,18 @@ typedef struct {
 } imin_instance;
 
 /*
- * imin_greedy_batch -- AdvancedGreedy (Algorithm 3) on `count` independent problems at once.
- * Round r of every instance that still has rounds left runs in the same launches: one
- * wave-per-sample launch over all their samples (samples that outgrow it go to the
- * workgroup kernel of their own graph), then one argmax per instance. Instance i's result
- * is bit-identical to imin_greedy(inst[i].g, S, nS, b, theta, seed, IMIN_AG, ...).
+ * imin_greedy_batch -- AdvancedGreedy (Algorithm 3) or GreedyReplace (Algorithm 4) on `count`
+ * independent problems at once. Round r of every instance that still has rounds left runs
+ * in the same launches: the wavefront-level kernels over all their samples (samples that
+ * outgrow them go to the workgroup kernel), then one argmax per instance, on the device.
+ * Under GreedyReplace an instance's round is a first-phase round or a replacement step, and
+ * its replacement pass stops on the device; the call reads back one word per round to end
+ * when every pass has stopped. Instance i's result is bit-identical to
+ * imin_greedy(inst[i].g, S, nS, b, theta, seed, mode, ...).
  * The batch's device scratch (workgroup slots sized for its largest instance, hand-over
  * lists) stays with inst[0].g after the call and serves the next batch that graph leads;
  * imin_graph_destroy releases it.
- *   mode    IMIN_AG only (IMIN_EINVAL otherwise).
+ *   mode    IMIN_AG or IMIN_GR, for every instance.
  *   count   >= 1; the total of theta over the batch must not exceed 2^31 (IMIN_ERANGE).
  *   launch  the wave kernel's launch shape (NULL: defaults); the graphs' own imin_set_small
  *           settings do not apply here.
@@ -261,9 +264,10 @@ IMIN_API int imin_greedy_batch(imin_instance *inst, int32_t count, int mode,
                                const imin_launch *launch);
 
 /*
- * Query server: AdvancedGreedy for a stream of queries against one resident graph, with
- * continuous batching (see imin_server_step). A query's blockers and counters are those of
- * imin_greedy(g, S, nS, b, theta, seed, IMIN_AG) alone, whatever else runs beside it.
+ * Query server: AdvancedGreedy or GreedyReplace for a stream of queries against one resident
+ * graph, with continuous batching (see imin_server_step). A query's blockers and counters
+ * are those of imin_greedy(g, S, nS, b, theta, seed, mode) alone, whatever else runs beside
+ * it.
  */
 typedef struct imin_server imin_server;
 
@@ -299,10 +303,20 @@ IMIN_API int imin_server_submit(imin_server *s, const int32_t *S, int32_t nS, in
                                 uint32_t theta, uint64_t seed, uint64_t *ticket);
 
 /*
+ * imin_server_submit_mode -- as imin_server_submit, with the greedy driver: IMIN_AG
+ * (Algorithm 3) or IMIN_GR (Algorithm 4; its replacement pass stops on the device, and the
+ * query retires at the step where it stops). Errors: as imin_server_submit, and IMIN_EINVAL
+ * for an unknown mode.
+ */
+IMIN_API int imin_server_submit_mode(imin_server *s, const int32_t *S, int32_t nS, int32_t b,
+                                     uint32_t theta, uint64_t seed, int mode, uint64_t *ticket);
+
+/*
  * imin_server_step -- one scheduling step: admit queued queries in arrival order while
  * their state fits the budget and fewer than max_active are admitted (a query that does
  * not fit waits, and so do the ones behind it); run one greedy round of every admitted
- * query in shared launches; retire the queries whose rounds are done. Returns when the
+ * query in shared launches; retire the queries whose rounds are done (GreedyReplace: or
+ * whose replacement pass stopped in this step). Returns when the
  * step's GPU work has finished. n_active / n_queued (nullable) receive the counts after
  * the step.
  */

@@ -116,6 +116,10 @@ def load() -> ctypes.CDLL:
     lib.imin_server_submit.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                        ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
     lib.imin_server_submit.restype = ctypes.c_int
+    lib.imin_server_submit_mode.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_uint64)]
+    lib.imin_server_submit_mode.restype = ctypes.c_int
     lib.imin_server_step.argtypes = [P, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32)]
     lib.imin_server_step.restype = ctypes.c_int
@@ -232,7 +236,7 @@ def imin_greedy(handle: int, seeds, b: int, theta: int, seed: int, mode: int):
 
 
 def imin_greedy_batch(problems, mode: int = IMIN_AG, launch=None):
-    """AdvancedGreedy on many problems at once. ``problems``: sequence of
+    """AdvancedGreedy or GreedyReplace on many problems at once. ``problems``: sequence of
     (handle, seeds, b, theta, seed); ``launch``: None or a dict of imin_launch fields.
     Returns a list of (blockers, stats dict)."""
     k = len(problems)
@@ -332,13 +336,14 @@ class Server:
             raise IminError("imin_server_query_bytes", rc)
         return out.value
 
-    def submit(self, seeds, b: int, theta: int, seed: int = 0) -> int:
+    def submit(self, seeds, b: int, theta: int, seed: int = 0, mode: int = IMIN_AG) -> int:
         S = np.ascontiguousarray(seeds, dtype=np.int32)
         t = ctypes.c_uint64()
-        rc = load().imin_server_submit(ctypes.c_void_p(self.handle), _p(S), S.shape[0], int(b),
-                                       int(theta), int(seed) & (2**64 - 1), ctypes.byref(t))
+        rc = load().imin_server_submit_mode(ctypes.c_void_p(self.handle), _p(S), S.shape[0],
+                                            int(b), int(theta), int(seed) & (2**64 - 1),
+                                            int(mode), ctypes.byref(t))
         if rc != IMIN_OK:
-            raise IminError("imin_server_submit", rc)
+            raise IminError("imin_server_submit_mode", rc)
         return t.value
 
     def step(self):

@@ -249,6 +249,9 @@ void describe(imin_graph *g, int32_t nseeds, uint64_t seed, uint32_t theta)
     I.x = g->d_x;
     I.thr_orig = g->d_thr_orig;
     I.ctrl = g->d_ctrl;
+    I.cand = g->d_cand;
+    I.gr_k = -1;
+    I.step = 0;
     I.nseeds = nseeds;
     I.n = g->n;
     I.nquads = (int32_t)std::max<int64_t>(((int64_t)g->m + 3) / 4, 1);
@@ -459,17 +462,38 @@ int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uin
     return IMIN_OK;
 }
 
+int32_t gr_candidates(const imin_graph *g, const std::vector<int32_t> &seeds,
+                      const std::vector<uint32_t> &inelig, std::vector<uint32_t> &cand)
+{
+    cand.assign((size_t)g->words, 0u);
+    int32_t ncb = 0;
+    for (int32_t s : seeds) {
+        for (int32_t e = g->row_ptr[s]; e < g->row_ptr[s + 1]; ++e) {
+            const int32_t v = g->col[e];
+            const bool is_seed = (inelig[v >> 5] >> (v & 31)) & 1u;
+            if (!is_seed && !((cand[v >> 5] >> (v & 31)) & 1u)) {
+                cand[v >> 5] |= 1u << (v & 31);
+                ++ncb;
+            }
+        }
+    }
+    return ncb;
+}
+
 int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst, uint32_t total,
-                uint32_t round, const imin_launch &shape, int num_cus, bool select,
-                int32_t slot, bool lt, hipStream_t stream)
+                uint32_t round, const imin_launch &shape, int num_cus, bool select, bool gr,
+                bool lt, hipStream_t stream)
 {
     if (total > ms.cap) return IMIN_ERANGE;
     const bool spill = ms.big_ws.slots > 0;
-    // every word but the error words 2 and 6 restarts every round; those accumulate
+    // words 0-5, 7 and 8 restart every round; the error words 2 and 6 accumulate, and word 9
+    // (instances done) over the call
     if (!ok(imin::launch_batch_zero(inst, ninst, stream)) ||
         !ok(imin::launch_fill_u32(ms.ctrl, 2, 0, stream)) ||
         !ok(imin::launch_fill_u32(ms.ctrl + 3, 3, 0, stream)) ||
-        !ok(imin::launch_fill_u32(ms.ctrl + 7, kMultiCtrl - 7, 0, stream)))
+        !ok(imin::launch_fill_u32(ms.ctrl + 7, 2, 0, stream)))
+        return IMIN_EDEVICE;
+    if (gr && !ok(imin::launch_batch_gr_prepare(inst, ninst, (int32_t)round, stream)))
         return IMIN_EDEVICE;
     // The smallest samples first, several to a wavefront (independent cascade only: the
     // packed kernel keeps the seed level's edge coins in registers); what outgrows it goes
@@ -540,7 +564,8 @@ int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst,
     }
     if (select) {
         if (ninst > ms.inst_cap) return IMIN_ERANGE;
-        if (!ok(imin::launch_batch_argmax(inst, ninst, slot, ms.part_d, ms.part_i, stream)))
+        if (!ok(imin::launch_batch_argmax(inst, ninst, (int32_t)round, ms.part_d, ms.part_i,
+                                          ms.ctrl + 9, stream)))
             return IMIN_EDEVICE;
     }
     return IMIN_OK;
@@ -765,7 +790,9 @@ struct BatchItem {
     imin_graph *g = nullptr;
     std::vector<int32_t> seeds;
     std::vector<uint32_t> inelig;
-    int32_t rounds = 0;
+    std::vector<uint32_t> cand;  // GreedyReplace: CB
+    int32_t rounds = 0;          // greedy rounds at most (GreedyReplace: 2k)
+    int32_t nb = 0;              // blocker slots (GreedyReplace: k)
 };
 
 // A stream capture that is always ended, and the graph it made, released at scope exit.
@@ -1099,19 +1126,9 @@ int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t
                                hipMemcpyDeviceToHost, g->stream)))
             return IMIN_EDEVICE;
     } else {
-        // CB: out-neighbours of the merged seed, seeds excluded (Algorithm 4, line 1).
-        std::vector<uint32_t> cand((size_t)g->words, 0u);
-        int32_t ncb = 0;
-        for (int32_t s : seeds) {
-            for (int32_t e = g->row_ptr[s]; e < g->row_ptr[s + 1]; ++e) {
-                const int32_t v = g->col[e];
-                const bool is_seed = (inelig[v >> 5] >> (v & 31)) & 1u;
-                if (!is_seed && !((cand[v >> 5] >> (v & 31)) & 1u)) {
-                    cand[v >> 5] |= 1u << (v & 31);
-                    ++ncb;
-                }
-            }
-        }
+        // CB: out-neighbours of the merged seed, seeds excluded (Algorithm 4).
+        std::vector<uint32_t> cand;
+        const int32_t ncb = gr_candidates(g, seeds, inelig, cand);
         if (!ok(hipMemcpyAsync(g->d_cand, cand.data(), cand.size() * sizeof(uint32_t),
                                hipMemcpyHostToDevice, g->stream)))
             return IMIN_EDEVICE;
@@ -1187,7 +1204,9 @@ int imin_set_small(imin_graph *g, int32_t enable, const imin_launch *launch)
 
 int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_launch *launch)
 {
-    if (!inst || count <= 0 || mode != IMIN_AG || !launch_ok(launch)) return IMIN_EINVAL;
+    if (!inst || count <= 0 || (mode != IMIN_AG && mode != IMIN_GR) || !launch_ok(launch))
+        return IMIN_EINVAL;
+    const bool gr = mode == IMIN_GR;
     const imin_launch shape = launch ? *launch : imin_launch{0, 0, 0, 0, 0};
     std::vector<BatchItem> items((size_t)count);
     std::vector<imin_graph *> graphs;
@@ -1203,7 +1222,14 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         it.g = in.g;
         int rc = seed_setup(in.g, in.S, in.nS, it.seeds, it.inelig);
         if (rc) return rc;
-        it.rounds = std::min<int32_t>(in.b, in.g->n - (int32_t)it.seeds.size());
+        if (gr) {
+            const int32_t k = std::min(gr_candidates(in.g, it.seeds, it.inelig, it.cand), in.b);
+            it.nb = k;
+            it.rounds = 2 * k;
+        } else {
+            it.rounds = std::min<int32_t>(in.b, in.g->n - (int32_t)it.seeds.size());
+            it.nb = it.rounds;
+        }
         theta_sum += in.theta;
         graphs.push_back(in.g);
     }
@@ -1228,18 +1254,21 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
     std::vector<imin::BatchStage> stages((size_t)count);
     std::vector<int32_t> stage, rounds((size_t)count);
     std::vector<uint32_t> prefix((size_t)count + 1, 0u);
-    int32_t max_rounds = 0;
+    int32_t max_rounds = 0, max_nb = 0, gr_runs = 0;
     for (int32_t i = 0; i < count; ++i) {
         BatchItem &it = items[(size_t)i];
         imin_graph *g = it.g;
-        const int rc = ensure_B(g, it.rounds);
+        const int rc = ensure_B(g, it.nb);
         if (rc) return rc;
         describe(g, (int32_t)it.seeds.size(), it.in->seed, it.in->theta);
         table[(size_t)i] = g->h_inst;
         table[(size_t)i].sample_base = prefix[(size_t)i];
+        table[(size_t)i].gr_k = gr ? it.nb : -1;
         prefix[(size_t)i + 1] = prefix[(size_t)i] + it.in->theta;
-        rounds[(size_t)i] = it.rounds;
+        rounds[(size_t)i] = it.nb;  // blocker slots gathered at the end
         max_rounds = std::max(max_rounds, it.rounds);
+        max_nb = std::max(max_nb, it.nb);
+        if (gr && it.nb > 0) ++gr_runs;
         imin::BatchStage &S = stages[(size_t)i];
         S.seeds = (int64_t)stage.size();
         stage.insert(stage.end(), it.seeds.begin(), it.seeds.end());
@@ -1256,8 +1285,13 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         S.now = (int64_t)stage.size();
         S.nnow = (int32_t)g->masked.size();
         stage.insert(stage.end(), g->masked.begin(), g->masked.end());
+        S.cand = -1;
+        if (gr) {
+            S.cand = (int64_t)stage.size();
+            for (uint32_t w : it.cand) stage.push_back((int32_t)w);
+        }
     }
-    const int32_t stride = imin::kGatherB + std::max(max_rounds, 1);
+    const int32_t stride = imin::kGatherB + std::max(max_nb, 1);
     DeviceBuf<imin::InstanceDesc> d_table;
     DeviceBuf<imin::BatchStage> d_stages;
     DeviceBuf<int32_t> d_stage, d_rounds, d_out;
@@ -1294,9 +1328,11 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
                            hipMemcpyHostToDevice, bs)) ||
         !ok(imin::launch_batch_setup(d_table.p, d_stages.p, d_stage.p, count, bs)))
         return IMIN_EDEVICE;
-    // Rounds: every launch is queued at once; nothing waits for the host until the end.
+    // Rounds: every launch is queued at once; nothing waits for the host until the end
+    // (GreedyReplace: one word read back per round, the count of runs that have ended).
     const bool lt = g0->model == IMIN_LT;
-    if (shape.graph) {
+    if (!ok(imin::launch_fill_u32(ms.ctrl + 9, 1, 0, bs))) return IMIN_EDEVICE;
+    if (shape.graph && !gr) {
         // One HIP graph of kernel nodes for all rounds (slots clear their own maps when
         // their epochs wrap, so no memset is ever needed inside).
         GraphCapture cap;
@@ -1306,7 +1342,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         for (int32_t r = 0; r < max_rounds; ++r) {
             while (act > 0 && items[(size_t)act - 1].rounds <= r) --act;
             rc = multi_round(ms, d_table.p, act, prefix[(size_t)act], (uint32_t)r, shape,
-                             g0->num_cus, true, r, lt, bs);
+                             g0->num_cus, true, false, lt, bs);
             if (rc) return rc;
         }
         rc = cap.finish();
@@ -1326,9 +1362,18 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
             if (rc) return rc;
             if (!ok(hipEventRecord(k0, bs))) return IMIN_EDEVICE;
             rc = multi_round(ms, d_table.p, active, prefix[(size_t)active], (uint32_t)r,
-                             shape, g0->num_cus, true, r, lt, bs);
+                             shape, g0->num_cus, true, gr, lt, bs);
             if (rc) return rc;
             if (!ok(hipEventRecord(k1, bs))) return IMIN_EDEVICE;
+            if (gr) {
+                // every replacement pass that can still run has stopped: no more rounds
+                uint32_t ended = 0;
+                if (!ok(hipMemcpyAsync(&ended, ms.ctrl + 9, sizeof(ended), hipMemcpyDeviceToHost,
+                                       bs)) ||
+                    !ok(hipStreamSynchronize(bs)))
+                    return IMIN_EDEVICE;
+                if ((int32_t)ended >= gr_runs) break;
+            }
         }
     }
     // Results: every graph's blocker slots, counters and error flag, gathered into one
@@ -1352,7 +1397,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
             st[(size_t)i][k] = (unsigned long long)(uint32_t)o[2 * k] |
                                ((unsigned long long)(uint32_t)o[2 * k + 1] << 32);
         err[(size_t)i] = (uint32_t)o[imin::kGatherErr];
-        B[(size_t)i].assign(o + imin::kGatherB, o + imin::kGatherB + items[(size_t)i].rounds);
+        B[(size_t)i].assign(o + imin::kGatherB, o + imin::kGatherB + items[(size_t)i].nb);
     }
     float total_ms = 0.0f;
     if (!ok(hipEventElapsedTime(&total_ms, g0->ev0, g0->ev1))) return IMIN_EDEVICE;
@@ -1371,7 +1416,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         BatchItem &it = items[(size_t)i];
         end_masks(it.g, B[(size_t)i]);
         std::copy(B[(size_t)i].begin(), B[(size_t)i].end(), it.in->blockers);
-        *it.in->n_blockers = it.rounds;
+        *it.in->n_blockers = it.nb;
         if (it.in->stats) {
             imin_stats &o = *it.in->stats;
             o.samples = st[(size_t)i][0];

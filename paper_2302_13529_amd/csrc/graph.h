@@ -126,7 +126,7 @@ int launch_large_on(imin_graph *g, const LargeTarget &t, uint32_t theta, uint64_
 // Device scratch of rounds over many instances at once (batched calls, the server): the
 // wave kernel's hand-over list, the workgroup kernel's slots (maps sized for the largest
 // instance) and its own overflow list, and the control words of one round.
-constexpr int kMultiCtrl = 9;
+constexpr int kMultiCtrl = 10;
 
 struct MultiScratch {
     int64_t n = 0, m = 0;      // largest instance it serves
@@ -134,7 +134,7 @@ struct MultiScratch {
     Workspace main_ws, big_ws;
     uint32_t *ctrl = nullptr;  // kMultiCtrl: wave next, wave hand-overs, wave error, main
                                // next, big next, overflow count, workgroup error, packed
-                               // hand-overs, packed next
+                               // hand-overs, packed next, instances done this call
     uint32_t *pi = nullptr, *pj = nullptr;  // packed kernel's hand-over list: instance, sample
     uint32_t *si = nullptr, *sj = nullptr;  // wave kernel's hand-over list: instance, sample
     uint32_t *oi = nullptr, *oj = nullptr;  // overflow list: instance, sample
@@ -146,12 +146,18 @@ int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uin
                 int32_t max_inst, hipStream_t stream);
 void multi_free(MultiScratch &ms);
 // One round of every instance of the device table inst[0..ninst) (sample indices
-// [0, total), keys seed + round): the wave kernel, the workgroup kernels for the samples it
-// hands over, then (select) the AdvancedGreedy choice of each instance written to B[slot].
-// Nothing waits for the host. D is cleared first.
+// [0, total), keys seed + round, greedy round step + round): for GreedyReplace instances in
+// their replacement pass (gr) the unblocking of that round's slot, then the wavefront-level
+// kernels, the workgroup kernels for the samples they hand over, then (select) each
+// instance's greedy choice, applied (launch_batch_argmax; instances that end their run add
+// one to ms.ctrl[9]). Nothing waits for the host. D is cleared first.
 int multi_round(MultiScratch &ms, const InstanceDesc *inst, int32_t ninst, uint32_t total,
-                uint32_t round, const imin_launch &shape, int num_cus, bool select,
-                int32_t slot, bool lt, hipStream_t stream);
+                uint32_t round, const imin_launch &shape, int num_cus, bool select, bool gr,
+                bool lt, hipStream_t stream);
+// GreedyReplace's first-phase candidates CB = out-neighbours of the seeds that are not
+// seeds, as a bitmap over g's vertices; returns |CB|.
+int32_t gr_candidates(const imin_graph *g, const std::vector<int32_t> &seeds,
+                      const std::vector<uint32_t> &inelig, std::vector<uint32_t> &cand);
 // The error words of the last rounds (0 when every sample was counted).
 int multi_errors(MultiScratch &ms, uint32_t *wave_err, uint32_t *wg_err, hipStream_t stream);
 

@@ -133,6 +133,11 @@ struct InstanceDesc {
     uint32_t *ctrl;           // kCtrlWords control words: the graph's workgroup-kernel
                               // counters in single calls; in many-instance launches see
                               // kCtrlSkipWave .. kCtrlPackHanded
+    uint32_t *cand;           // GreedyReplace: its first phase's candidate set CB (bit v set)
+    int32_t gr_k;             // GreedyReplace: rounds of its first phase, k = min(|CB|, b);
+                              // -1: AdvancedGreedy
+    int32_t step;             // the instance's round is step + the launch's round (the call
+                              // index of its greedy run; blocker slot of AdvancedGreedy)
     int32_t nseeds;
     int32_t n;
     int32_t nquads;           // quads of thr4
@@ -148,6 +153,8 @@ constexpr int kCtrlWaveHanded = 1;  // samples the wave kernel handed over this 
 constexpr int kCtrlError = 3;       // nonzero: a sample was lost (never expected)
 constexpr int kCtrlSkipPack = 4;    // 1: the packed kernel lists the instance's samples onward
 constexpr int kCtrlPackHanded = 5;  // samples the packed kernel handed over this round
+constexpr int kCtrlDone = 6;        // 1: the instance's greedy run has ended (GreedyReplace's
+                                    // replacement pass stopped); its samples are skipped
 
 struct SmallArgs {
     const InstanceDesc *inst; // ascending sample_base
@@ -235,6 +242,7 @@ hipError_t launch_batch_zero(const InstanceDesc *inst, int32_t ninst, hipStream_
 struct BatchStage {
     int64_t seeds, bits, prev, now;
     int32_t words, nprev, nnow, pad;
+    int64_t cand;  // GreedyReplace: CB bitmap at [cand, cand + words); -1: none
 };
 // One workgroup per instance: copy seeds and bitmap into place, clear the counters and
 // control words, restore the previous masks, then mask the new ones.
@@ -244,17 +252,33 @@ hipError_t launch_batch_setup(const InstanceDesc *inst, const BatchStage *st,
 // instance i into out + i * stride (int32 words; counters as pairs of words).
 hipError_t launch_batch_gather(const InstanceDesc *inst, const int32_t *rounds, int32_t *out,
                                int32_t stride, int32_t ninst, hipStream_t stream);
-// The AdvancedGreedy choice of every instance, written to B[slot] and applied (bitmap bit,
-// in-edge masks, *x): kArgParts workgroups per instance scan a share of its D each and
-// leave their best (D, vertex) in part_d/part_i (ninst * kArgParts entries); one workgroup
-// per instance then reduces them.
+// The greedy choice of every instance in its round (step + round) and its application:
+// kArgParts workgroups per instance scan a share of its D each and leave their best
+// (D, vertex) in part_d/part_i (ninst * kArgParts entries); one workgroup per instance then
+// reduces them and applies the winner x (bitmap bit, in-edge masks, *x):
+//   AdvancedGreedy (Algorithm 3): argmax over V \ (S u B) into B[step];
+//   GreedyReplace (Algorithm 4), first phase (step < k): argmax over the remaining CB into
+//     B[step], x leaves CB;
+//   GreedyReplace, replacement pass (k <= step < 2k): slot i = 2k - 1 - step, whose blocker
+//     u was unblocked before the round's samples (launch_batch_gr_prepare); argmax over
+//     V \ (S u B) into B[i]; the instance is done when x == u or i == 0 (*done_count + 1).
+// Instances already done are skipped.
 constexpr int kArgParts = 16;
 // Layout of one instance's record in the batch gather buffer (int32 words): the kGatherStats
 // 64-bit counters as pairs of words, the error word, then the blocker slots.
 constexpr int kGatherStats = 7;
 constexpr int kGatherErr = 2 * kGatherStats;
 constexpr int kGatherB = kGatherErr + 1;
-hipError_t launch_batch_argmax(const InstanceDesc *inst, int32_t ninst, int32_t slot,
-                               unsigned long long *part_d, int32_t *part_i, hipStream_t stream);
+hipError_t launch_batch_argmax(const InstanceDesc *inst, int32_t ninst, int32_t round,
+                               unsigned long long *part_d, int32_t *part_i, uint32_t *done_count,
+                               hipStream_t stream);
+// GreedyReplace instances in their replacement pass: unblock the blocker of slot
+// 2k - 1 - (step + round) (bitmap bit cleared, in-edge thresholds restored) before the
+// round's samples. Other instances are left alone.
+hipError_t launch_batch_gr_prepare(const InstanceDesc *inst, int32_t ninst, int32_t round,
+                                   hipStream_t stream);
+// out[i] = the done word of instance i.
+hipError_t launch_batch_done(const InstanceDesc *inst, int32_t ninst, uint32_t *out,
+                             hipStream_t stream);
 
 }  // namespace imin

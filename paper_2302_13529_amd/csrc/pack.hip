@@ -469,6 +469,7 @@ __global__ __launch_bounds__(kPackBlock) void decrease_pack_kernel(PackArgs a)
     InstanceDesc I{};
     uint32_t cur_lo = 0, cur_hi = 0;
     bool skip = false;  // the current instance's samples go straight to the next kernel
+    bool done = false;  // the current instance's greedy run has ended: its samples are dropped
     SeedCache sc;
     sc.total = -1;
     Tally tally{0, 0, 0, 0};
@@ -510,7 +511,12 @@ __global__ __launch_bounds__(kPackBlock) void decrease_pack_kernel(PackArgs a)
                 skip = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
                            &I.ctrl[kCtrlSkipPack], __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT)) != 0u;
-                if (!skip) {
+                done = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                           &I.ctrl[kCtrlDone], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT)) != 0u;
+                if (done) {
+                    sc.total = -1;
+                } else if (!skip) {
                     build_seed_cache(I, pw.e0, pw.e1, pw.ex, sc);
                     skip = sc.total < 0;
                 } else {
@@ -519,6 +525,10 @@ __global__ __launch_bounds__(kPackBlock) void decrease_pack_kernel(PackArgs a)
             }
             const uint32_t end = min(last, cur_hi);
             const uint32_t j0 = idx - cur_lo;
+            if (done) {
+                idx = end;
+                continue;
+            }
             if (skip) {
                 const uint32_t cnt = end - idx;
                 uint32_t pos = 0;

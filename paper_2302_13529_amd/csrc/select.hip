@@ -144,31 +144,38 @@ __global__ void batch_zero_kernel(const InstanceDesc *inst)
 
 // Workgroup blockIdx.x scans share blockIdx.x % kArgParts of instance blockIdx.x / kArgParts
 // (a multiple of 4 vertices); each thread takes 4 vertices at a time so that several loads
-// are in flight.
-__global__ void batch_argmax_part_kernel(const InstanceDesc *inst, unsigned long long *part_d,
-                                         int32_t *part_i)
+// are in flight. The candidates are the instance's CB in GreedyReplace's first phase, else
+// the vertices whose seed/blocked bit is clear.
+__global__ void batch_argmax_part_kernel(const InstanceDesc *inst, int32_t round,
+                                         unsigned long long *part_d, int32_t *part_i)
 {
     const InstanceDesc &I = inst[blockIdx.x / kArgParts];
     const int32_t k = (int32_t)(blockIdx.x % kArgParts);
-    const int32_t per = (((I.n + kArgParts - 1) / kArgParts) + 3) & ~3;
-    const int32_t lo = k * per;
-    const int32_t hi = min(I.n, lo + per);
     unsigned long long bd = 0;
     int bi = -1;
-    constexpr int kStep = 4 * kSelBlock;
-    for (int32_t base = lo + 4 * (int32_t)threadIdx.x; base < hi; base += kStep) {
-        unsigned long long d[4];
-        uint32_t w[4];
+    if (I.ctrl[kCtrlDone] == 0u) {
+        const int32_t step = I.step + round;
+        const bool in_cb = I.gr_k >= 0 && step < I.gr_k;
+        const uint32_t *bits = in_cb ? I.cand : I.inelig;
+        const uint32_t flip = in_cb ? 0xFFFFFFFFu : 0u;  // candidates: bit set in CB, clear else
+        const int32_t per = (((I.n + kArgParts - 1) / kArgParts) + 3) & ~3;
+        const int32_t lo = k * per;
+        const int32_t hi = min(I.n, lo + per);
+        constexpr int kStep = 4 * kSelBlock;
+        for (int32_t base = lo + 4 * (int32_t)threadIdx.x; base < hi; base += kStep) {
+            unsigned long long d[4];
+            uint32_t w[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int32_t v = base + k;
-            d[k] = v < hi ? I.D[v] : 0ull;
-            w[k] = v < hi ? I.inelig[v >> 5] : 0xFFFFFFFFu;
-        }
+            for (int q = 0; q < 4; ++q) {
+                const int32_t v = base + q;
+                d[q] = v < hi ? I.D[v] : 0ull;
+                w[q] = v < hi ? (bits[v >> 5] ^ flip) : 0xFFFFFFFFu;
+            }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int32_t v = base + k;
-            if (v < hi && !((w[k] >> (v & 31)) & 1u)) better(bd, bi, d[k], (int)v);
+            for (int q = 0; q < 4; ++q) {
+                const int32_t v = base + q;
+                if (v < hi && !((w[q] >> (v & 31)) & 1u)) better(bd, bi, d[q], (int)v);
+            }
         }
     }
     block_best(bd, bi);
@@ -179,12 +186,12 @@ __global__ void batch_argmax_part_kernel(const InstanceDesc *inst, unsigned long
 }
 
 // One workgroup per instance: the best of its kArgParts shares, applied. It also ends the
-// instance's round for the wave kernel: when that kernel handed over more than half of the
-// instance's samples (control word 1), later rounds send them straight to the workgroup
-// kernel (control word 0).
+// instance's round for the wavefront-level kernels: when one of them handed over more than
+// half of the instance's samples, later rounds send them straight past it.
 __global__ void batch_argmax_apply_kernel(const InstanceDesc *inst,
                                           const unsigned long long *part_d,
-                                          const int32_t *part_i, int32_t slot)
+                                          const int32_t *part_i, int32_t round,
+                                          uint32_t *done_count)
 {
     const InstanceDesc &I = inst[blockIdx.x];
     unsigned long long bd = 0;
@@ -193,6 +200,7 @@ __global__ void batch_argmax_apply_kernel(const InstanceDesc *inst,
         better(bd, bi, part_d[blockIdx.x * kArgParts + threadIdx.x],
                part_i[blockIdx.x * kArgParts + threadIdx.x]);
     block_best(bd, bi);
+    __shared__ int s_go;
     if (threadIdx.x == 0) {
         if (2ull * I.ctrl[kCtrlWaveHanded] > (unsigned long long)I.theta)
             I.ctrl[kCtrlSkipWave] = 1u;
@@ -200,13 +208,56 @@ __global__ void batch_argmax_apply_kernel(const InstanceDesc *inst,
         if (2ull * I.ctrl[kCtrlPackHanded] > (unsigned long long)I.theta)
             I.ctrl[kCtrlSkipPack] = 1u;
         I.ctrl[kCtrlPackHanded] = 0u;
-        if (bi >= 0) {
-            I.inelig[bi >> 5] |= 1u << (bi & 31);
-            I.B[slot] = bi;
+        s_go = 0;
+        if (I.ctrl[kCtrlDone] == 0u) {
+            const int32_t step = I.step + round;
+            int32_t slot = step;
+            bool last = false;
+            int32_t u = -1;
+            if (I.gr_k >= 0 && step >= I.gr_k) {
+                slot = 2 * I.gr_k - 1 - step;
+                u = I.B[slot];
+                last = slot == 0;
+            } else if (I.gr_k >= 0) {
+                if (bi >= 0) I.cand[bi >> 5] &= ~(1u << (bi & 31));
+                last = false;
+            }
+            if (bi >= 0) {
+                I.inelig[bi >> 5] |= 1u << (bi & 31);
+                I.B[slot] = bi;
+                s_go = 1;
+            }
+            *I.x = bi;
+            if (I.gr_k >= 0 && step >= I.gr_k && (bi == u || bi < 0 || last)) {
+                I.ctrl[kCtrlDone] = 1u;
+                if (done_count) atomicAdd(done_count, 1u);
+            }
         }
-        *I.x = bi;
     }
-    if (bi >= 0) mask_in_edges(reinterpret_cast<uint32_t *>(I.thr4), I.in_ptr, I.in_edge, bi);
+    __syncthreads();
+    if (s_go) mask_in_edges(reinterpret_cast<uint32_t *>(I.thr4), I.in_ptr, I.in_edge, bi);
+}
+
+// One workgroup per instance in GreedyReplace's replacement pass: unblock the blocker u of
+// this round's slot before the round's samples are drawn.
+__global__ void batch_gr_prepare_kernel(const InstanceDesc *inst, int32_t round)
+{
+    const InstanceDesc &I = inst[blockIdx.x];
+    if (I.gr_k < 0 || I.ctrl[kCtrlDone] != 0u) return;
+    const int32_t step = I.step + round;
+    if (step < I.gr_k || step >= 2 * I.gr_k) return;
+    const int32_t u = I.B[2 * I.gr_k - 1 - step];
+    if (threadIdx.x == 0) I.inelig[u >> 5] &= ~(1u << (u & 31));
+    uint32_t *thr = reinterpret_cast<uint32_t *>(I.thr4);
+    const uint32_t *orig = reinterpret_cast<const uint32_t *>(I.thr_orig);
+    for (int32_t k = I.in_ptr[u] + threadIdx.x; k < I.in_ptr[u + 1]; k += kSelBlock)
+        thr[I.in_edge[k]] = orig[I.in_edge[k]];
+}
+
+__global__ void batch_done_kernel(const InstanceDesc *inst, int32_t ninst, uint32_t *out)
+{
+    const int32_t i = blockIdx.x * kSelBlock + threadIdx.x;
+    if (i < ninst) out[i] = inst[i].ctrl[kCtrlDone];
 }
 
 __global__ void batch_setup_kernel(const InstanceDesc *inst, const BatchStage *st,
@@ -218,6 +269,9 @@ __global__ void batch_setup_kernel(const InstanceDesc *inst, const BatchStage *s
     for (int32_t k = threadIdx.x; k < I.nseeds; k += kSelBlock) seeds[k] = stage[S.seeds + k];
     for (int32_t k = threadIdx.x; k < S.words; k += kSelBlock)
         I.inelig[k] = (uint32_t)stage[S.bits + k];
+    if (S.cand >= 0)
+        for (int32_t k = threadIdx.x; k < S.words; k += kSelBlock)
+            I.cand[k] = (uint32_t)stage[S.cand + k];
     if (threadIdx.x < kGatherStats) I.stats[threadIdx.x] = 0ull;
     if (threadIdx.x < kCtrlWords) I.ctrl[threadIdx.x] = 0u;
     uint32_t *thr = reinterpret_cast<uint32_t *>(I.thr4);
@@ -326,14 +380,33 @@ hipError_t launch_batch_zero(const InstanceDesc *inst, int32_t ninst, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_batch_argmax(const InstanceDesc *inst, int32_t ninst, int32_t slot,
-                               unsigned long long *part_d, int32_t *part_i, hipStream_t stream)
+hipError_t launch_batch_argmax(const InstanceDesc *inst, int32_t ninst, int32_t round,
+                               unsigned long long *part_d, int32_t *part_i, uint32_t *done_count,
+                               hipStream_t stream)
 {
     if (ninst <= 0) return hipSuccess;
     hipLaunchKernelGGL(batch_argmax_part_kernel, dim3(ninst * kArgParts), dim3(kSelBlock), 0,
-                       stream, inst, part_d, part_i);
+                       stream, inst, round, part_d, part_i);
     hipLaunchKernelGGL(batch_argmax_apply_kernel, dim3(ninst), dim3(kSelBlock), 0, stream, inst,
-                       part_d, part_i, slot);
+                       part_d, part_i, round, done_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_gr_prepare(const InstanceDesc *inst, int32_t ninst, int32_t round,
+                                   hipStream_t stream)
+{
+    if (ninst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_gr_prepare_kernel, dim3(ninst), dim3(kSelBlock), 0, stream, inst,
+                       round);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_done(const InstanceDesc *inst, int32_t ninst, uint32_t *out,
+                             hipStream_t stream)
+{
+    if (ninst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_done_kernel, dim3((ninst + kSelBlock - 1) / kSelBlock),
+                       dim3(kSelBlock), 0, stream, inst, ninst, out);
     return hipGetLastError();
 }
 

@@ -1,17 +1,18 @@
-// server.cpp -- the query server of libimin: AdvancedGreedy (Algorithm 3 of arXiv
-// 2302.13529) for a stream of (S, b, theta, seed) queries against one resident graph, with
-// continuous batching.
+// server.cpp -- the query server of libimin: AdvancedGreedy or GreedyReplace (Algorithms 3
+// and 4 of arXiv 2302.13529) for a stream of (S, b, theta, seed) queries against one
+// resident graph, with continuous batching.
 //
 // Every query owns its state on the device: a copy of the graph's live thresholds (its seeds
 // and blockers get threshold 0 on their in-edges, as in a single call), the seed/blocked
 // bitmap, its seeds, counters D, work counters and blocker slots. That state is carved out
 // of one pool allocated when the server starts; a queued query is admitted, in arrival
 // order, as soon as its state fits in the pool and a slot is free. A step runs one greedy
-// round of every admitted query in shared launches (the wave kernel over all their samples,
-// the workgroup kernels for the samples it hands over, one argmax per query), then retires
-// the queries that have made all their rounds. A query's key for round r is seed + r, so a
-// query's blockers and counters are those of imin_greedy alone, whatever else shares its
-// steps.
+// round of every admitted query in shared launches (the wavefront-level kernels over all
+// their samples, the workgroup kernels for the samples they hand over, one argmax per query),
+// then retires the queries that have made all their rounds -- or, under GreedyReplace, whose
+// replacement pass has stopped (a device-side flag read back with the step). A query's key
+// for round r is seed + r, so a query's blockers and counters are those of imin_greedy alone,
+// whatever else shares its steps.
 #include "graph.h"
 
 #include <algorithm>
@@ -96,7 +97,10 @@ struct Query {
     uint64_t ticket = 0;
     std::vector<int32_t> seeds;
     std::vector<uint32_t> inelig;
+    std::vector<uint32_t> cand;  // GreedyReplace: CB
     int32_t b = 0, rounds = 0, round = 0;
+    int32_t mode = IMIN_AG;
+    int32_t nb = 0;              // blocker slots (GreedyReplace: k)
     uint32_t theta = 0;
     uint64_t seed = 0;
     size_t off = 0, bytes = 0;
@@ -138,11 +142,12 @@ struct imin_server {
 
 namespace {
 
-// Pool bytes of one query: thresholds, bitmap, seeds, D, counters, control words, blockers.
+// Pool bytes of one query: thresholds, bitmap, candidate bitmap, seeds, D, counters, control
+// words, blockers.
 size_t footprint(const imin_graph *g, int32_t nseeds, int32_t b)
 {
     const size_t quads = (size_t)std::max<int64_t>(((int64_t)g->m + 3) / 4, 1);
-    return align_up(quads * sizeof(uint4)) + align_up((size_t)g->words * 4) +
+    return align_up(quads * sizeof(uint4)) + 2 * align_up((size_t)g->words * 4) +
            align_up((size_t)std::max(nseeds, 1) * 4) + align_up((size_t)g->n * 8) +
            align_up(kStats * 8) + align_up(imin::kCtrlWords * 4) + align_up((size_t)std::max(b, 1) * 4) +
            align_up(4);
@@ -159,6 +164,8 @@ void carve(imin_server *s, Query &q)
     I.thr4 = reinterpret_cast<uint4 *>(p);
     p += align_up(quads * sizeof(uint4));
     I.inelig = reinterpret_cast<uint32_t *>(p);
+    p += align_up((size_t)g->words * 4);
+    I.cand = reinterpret_cast<uint32_t *>(p);
     p += align_up((size_t)g->words * 4);
     I.seeds = reinterpret_cast<int32_t *>(p);
     p += align_up((size_t)std::max<size_t>(q.seeds.size(), 1) * 4);
@@ -181,6 +188,8 @@ void carve(imin_server *s, Query &q)
     I.n = g->n;
     I.nquads = (int32_t)quads;
     I.theta = q.theta;
+    I.gr_k = q.mode == IMIN_GR ? q.nb : -1;
+    I.step = 0;
 }
 
 template <class T>
@@ -247,6 +256,11 @@ int admit(imin_server *s)
         st.now = (int64_t)s->stage.size();
         st.nnow = (int32_t)q.seeds.size();
         s->stage.insert(s->stage.end(), q.seeds.begin(), q.seeds.end());
+        st.cand = -1;
+        if (q.mode == IMIN_GR) {
+            st.cand = (int64_t)s->stage.size();
+            for (uint32_t w : q.cand) s->stage.push_back((int32_t)w);
+        }
         s->stages.push_back(st);
         s->table.push_back(q.desc);
     }
@@ -279,8 +293,8 @@ int retire(imin_server *s)
     s->rounds.clear();
     for (size_t i : fin) {
         s->table.push_back(s->active[i].desc);
-        s->rounds.push_back(s->active[i].rounds);
-        max_rounds = std::max(max_rounds, s->active[i].rounds);
+        s->rounds.push_back(s->active[i].nb);
+        max_rounds = std::max(max_rounds, s->active[i].nb);
     }
     const int32_t stride = imin::kGatherB + max_rounds;
     const size_t k = fin.size();
@@ -302,7 +316,7 @@ int retire(imin_server *s)
         const int32_t *o = s->out.data() + t * (size_t)stride;
         if (o[imin::kGatherErr] != 0) return IMIN_EDEVICE;
         Result r;
-        r.B.assign(o + imin::kGatherB, o + imin::kGatherB + q.rounds);
+        r.B.assign(o + imin::kGatherB, o + imin::kGatherB + q.nb);
         for (int32_t v : r.B)
             if (v < 0) return IMIN_EDEVICE;
         unsigned long long st[kStats];
@@ -388,13 +402,27 @@ int imin_server_query_bytes(const imin_server *s, int32_t nS, int32_t b, uint64_
 int imin_server_submit(imin_server *s, const int32_t *S, int32_t nS, int32_t b, uint32_t theta,
                        uint64_t seed, uint64_t *ticket)
 {
+    return imin_server_submit_mode(s, S, nS, b, theta, seed, IMIN_AG, ticket);
+}
+
+int imin_server_submit_mode(imin_server *s, const int32_t *S, int32_t nS, int32_t b,
+                            uint32_t theta, uint64_t seed, int mode, uint64_t *ticket)
+{
     if (!s || !ticket || theta == 0 || b < 0) return IMIN_EINVAL;
+    if (mode != IMIN_AG && mode != IMIN_GR) return IMIN_EINVAL;
     if (theta > s->cfg.max_theta) return IMIN_ERANGE;
     Query q;
     int rc = seed_setup(s->g, S, nS, q.seeds, q.inelig);
     if (rc) return rc;
     q.b = b;
-    q.rounds = std::min<int32_t>(b, s->g->n - (int32_t)q.seeds.size());
+    q.mode = mode;
+    if (mode == IMIN_GR) {
+        q.nb = std::min(gr_candidates(s->g, q.seeds, q.inelig, q.cand), b);
+        q.rounds = 2 * q.nb;
+    } else {
+        q.rounds = std::min<int32_t>(b, s->g->n - (int32_t)q.seeds.size());
+        q.nb = q.rounds;
+    }
     q.theta = theta;
     q.seed = seed;
     q.bytes = footprint(s->g, (int32_t)q.seeds.size(), b);
@@ -415,31 +443,49 @@ int imin_server_step(imin_server *s, int32_t *n_active, int32_t *n_queued)
     rc = retire(s);  // queries with no rounds at all
     if (rc) return rc;
     if (!s->active.empty()) {
-        // one greedy round of every active query: key seed + round, choice into B[round]
+        // one greedy round of every active query: key seed + round, its greedy round r
         s->table.clear();
         uint32_t total = 0;
+        bool gr = false;
         for (Query &q : s->active) {
             imin::InstanceDesc I = q.desc;
             const uint64_t key = q.seed + (uint64_t)q.round;
             I.seed_lo = (uint32_t)key;
             I.seed_hi = (uint32_t)(key >> 32);
-            I.B = q.desc.B + q.round;
+            I.step = q.round;
             I.sample_base = total;
             total += q.theta;
             s->table.push_back(I);
+            gr = gr || q.mode == IMIN_GR;
         }
         if (!ok(hipMemcpyAsync(s->d_table, s->table.data(),
                                s->table.size() * sizeof(s->table[0]), hipMemcpyHostToDevice,
                                s->stream)))
             return IMIN_EDEVICE;
         rc = multi_round(s->ms, s->d_table, (int32_t)s->active.size(), total, 0u, s->cfg.launch,
-                         s->g->num_cus, true, 0, s->g->model == IMIN_LT, s->stream);
+                         s->g->num_cus, true, gr, s->g->model == IMIN_LT, s->stream);
         if (rc) return rc;
+        // GreedyReplace queries whose replacement pass stopped this step end now
+        const size_t na = s->active.size();
+        if (gr) {
+            rc = ensure_dev(s->d_out, s->out_cap, na);
+            if (rc) return rc;
+            s->out.assign(na, 0);
+            if (!ok(imin::launch_batch_done(s->d_table, (int32_t)na,
+                                            reinterpret_cast<uint32_t *>(s->d_out), s->stream)) ||
+                !ok(hipMemcpyAsync(s->out.data(), s->d_out, na * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, s->stream)))
+                return IMIN_EDEVICE;
+        }
         uint32_t wave_err = 0, wg_err = 0;
         rc = multi_errors(s->ms, &wave_err, &wg_err, s->stream);  // waits for the step
         if (rc) return rc;
         if (wave_err || wg_err) return IMIN_EDEVICE;
-        for (Query &q : s->active) ++q.round;
+        for (size_t i = 0; i < na; ++i) {
+            Query &q = s->active[i];
+            ++q.round;
+            if (gr && s->out[i] != 0) q.round = q.rounds;
+        }
         rc = retire(s);
         if (rc) return rc;
     }

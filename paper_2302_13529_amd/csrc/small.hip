@@ -340,6 +340,7 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
     InstanceDesc I{};
     uint32_t cur_lo = 0, cur_hi = 0;
     bool skip = false;  // the current instance's samples go straight to the large kernel
+    bool done = false;  // many-instance launches: the instance's greedy run has ended
     SeedCache sc;
     sc.total = -1;
     Tally tally{0, 0, 0, 0};
@@ -392,12 +393,22 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
                        __builtin_amdgcn_readfirstlane(__hip_atomic_load(
                            &I.ctrl[kCtrlSkipWave], __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT)) != 0u;
+                done = a.spill_inst &&
+                       __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                           &I.ctrl[kCtrlDone], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT)) != 0u;
+                if (done) skip = true;
                 // LT: vertex-keyed choices, no quad cache; listed samples come in no
                 // particular instance order, so they read the seed rows from memory
                 if (kLT || skip || listed) sc.total = -1;
                 else build_seed_cache(I, ws.e0, ws.e1, ws.ex, sc);
             }
             if (!listed) j = idx - cur_lo;
+            if (done) {
+                // dropped: the rest of the run within this instance (list mode: this one)
+                idx += (listed ? 1u : min(last, cur_hi) - idx) - 1;
+                continue;
+            }
             if (skip) {
                 // the rest of the run within this instance, listed at once (list mode:
                 // this one sample)

@@ -22,9 +22,9 @@ def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
 
 
 def run(server: binding.Server, queries, arrivals=None, clock=time.perf_counter):
-    """Serve `queries` (dicts with seeds, b, theta, seed). With arrivals None every query is
-    submitted at time 0 (saturation). Returns (results, latencies, makespan, steps): results
-    and latencies in query order."""
+    """Serve `queries` (dicts with seeds, b, theta, seed, and optionally mode: AdvancedGreedy
+    by default). With arrivals None every query is submitted at time 0 (saturation). Returns
+    (results, latencies, makespan, steps): results and latencies in query order."""
     n = len(queries)
     arrivals = np.zeros(n) if arrivals is None else np.asarray(arrivals, dtype=np.float64)
     order = np.argsort(arrivals, kind="stable")
@@ -39,7 +39,8 @@ def run(server: binding.Server, queries, arrivals=None, clock=time.perf_counter)
         while nxt < n and arrivals[order[nxt]] <= now:
             i = int(order[nxt])
             q = queries[i]
-            t = server.submit(q["seeds"], q["b"], q["theta"], q["seed"])
+            t = server.submit(q["seeds"], q["b"], q["theta"], q["seed"],
+                              q.get("mode", binding.IMIN_AG))
             pending[t] = i
             nxt += 1
         if not pending:

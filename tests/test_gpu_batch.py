@@ -167,7 +167,7 @@ def test_batch_errors_leave_outputs_untouched(gpu):
         gpu.imin_greedy_batch([(g.handle, [0], 2, 10, 0), (g.handle, [1], 2, 10, 0)])
     assert e.value.status == gpu.IMIN_EINVAL
     with pytest.raises(gpu.IminError) as e:
-        gpu.imin_greedy_batch([(g.handle, [0], 2, 10, 0)], mode=gpu.IMIN_GR)
+        gpu.imin_greedy_batch([(g.handle, [0], 2, 10, 0)], mode=7)
     assert e.value.status == gpu.IMIN_EINVAL
     for bad in ((g.handle, [25], 2, 10, 0), (g.handle, [0], -1, 10, 0), (g.handle, [0], 2, 0, 0)):
         with pytest.raises(gpu.IminError) as e:
@@ -316,5 +316,31 @@ def test_packed_kernel_capacity_edges(gpu):
             assert st["pack_samples"] == st["samples"], name
         elif fits is False:
             assert st["pack_samples"] == 0, name
+    for g in graphs:
+        g.close()
+
+
+def test_batch_greedy_replace_equals_plain_and_oracle(gpu, batch16):
+    """GreedyReplace (Algorithm 4) on 16 instances in one batched call: first phase over each
+    instance's CB, then the replacement pass, which stops on the device per instance."""
+    insts = batch16
+    graphs = [gpu.Graph(t.row_ptr, t.col, t.prob) for t in insts]
+    bs = [0, 1, 5, 3, 5, 2, 4, 5, 1, 5, 3, 5, 5, 2, 4, 5]
+    thetas = [300, 500, 257, 300, 1000, 64, 300, 300, 999, 300, 300, 128, 300, 300, 700, 300]
+    probs = [(g.handle, t.seeds, b, th, t.seed) for g, t, b, th in zip(graphs, insts, bs, thetas)]
+    case("batched GR over 16 instances")
+    res = gpu.imin_greedy_batch(probs, gpu.IMIN_GR)
+    for i, (t, g, b, th) in enumerate(zip(insts, graphs, bs, thetas)):
+        B, st = res[i]
+        Bp, sp = g.greedy(t.seeds, b, th, t.seed, gpu.IMIN_GR)
+        assert list(B) == list(Bp), i
+        for k in ("samples", "reached", "edges_scanned", "live_edges"):
+            assert st[k] == sp[k], (i, k)
+        if i % 3 == 0:
+            case(f"instance {i} (n={t.n}, b={b}, theta={th}) against the oracle")
+            Bo, calls, so = orc.greedy(t.n, t.row_ptr, t.col, t.prob, t.seeds, b, th, t.seed,
+                                       orc.GR)
+            assert list(B) == list(Bo), i
+            assert st["samples"] == calls * th and st["reached"] == so["reached"], i
     for g in graphs:
         g.close()

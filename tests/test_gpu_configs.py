@@ -110,3 +110,35 @@ def test_served_subset_full_budgets(gpu):
         assert _stats(st) == wst, i
     srv.close()
     g.close()
+
+
+def test_rmat17_greedy_replace_batched_and_served(gpu):
+    """GreedyReplace at b = 100, theta = 10^4 on the 2^17-vertex R-MAT graph through the
+    batched call (a batch with a second, smaller instance) and through the server, against
+    the checker's full run."""
+    want = H.read_config_golden("config_c2_gr.txt")
+    t = H.cached("rmat17", gg.rmat_plain)
+    g = gpu.Graph(t.row_ptr, t.col, t.prob)
+    tiny = gg.tiny_plain()
+    g2 = gpu.Graph(tiny.row_ptr, tiny.col, tiny.prob)
+    case("rmat17 GR b=100 theta=10^4 in a batch of two")
+    res = gpu.imin_greedy_batch([(g.handle, t.seeds, t.b, t.theta, t.seed),
+                                 (g2.handle, tiny.seeds, 3, 500, 2)], gpu.IMIN_GR)
+    B, st = res[0]
+    assert [int(x) for x in B] == want["blockers"]
+    assert _stats(st) == want["stats"]
+    case("rmat17 GR b=100 theta=10^4 in the server, beside an AG query")
+    srv = gpu.Server(g, hbm_budget=2 << 30, max_active=4, max_theta=10000)
+    tk = srv.submit(t.seeds, t.b, t.theta, t.seed, mode=gpu.IMIN_GR)
+    tk2 = srv.submit(t.seeds[:3], 5, 2000, 9)
+    while srv.step() != (0, 0):
+        pass
+    B, st = srv.result(tk, t.b)
+    assert [int(x) for x in B] == want["blockers"]
+    assert _stats(st) == want["stats"]
+    B2, _ = srv.result(tk2, 5)
+    B2p, _ = g.greedy(t.seeds[:3], 5, 2000, 9, gpu.IMIN_AG)
+    assert list(B2) == list(B2p)
+    srv.close()
+    g.close()
+    g2.close()

@@ -154,3 +154,34 @@ def test_server_degenerate_queries(gpu):
     assert len(res[0][0]) == 0 and len(res[1][0]) == 0
     srv.close()
     g.close()
+
+
+def test_server_greedy_replace_mixed_with_advanced_greedy(gpu):
+    """GreedyReplace queries (Algorithm 4) in the server beside AdvancedGreedy ones: each
+    equals imin_greedy alone with its mode, and a few equal the checker."""
+    t = gg.tiny_plain()
+    g = gpu.Graph(t.row_ptr, t.col, t.prob)
+    qs = _queries(t.n, 30, 4, bmax=8)
+    for i, q in enumerate(qs):
+        q["mode"] = gpu.IMIN_GR if i % 2 == 0 else gpu.IMIN_AG
+    srv = gpu.Server(g, max_active=6, max_theta=1000)
+    case("tiny: 30 queries, GR and AG alternating, at most 6 at a time")
+    arrivals = np.linspace(0.0, 0.03, len(qs))
+    res, lat, span, steps = serve.run(srv, qs, arrivals)
+    for i, q in enumerate(qs):
+        B, st = res[i]
+        Bp, sp = g.greedy(q["seeds"], q["b"], q["theta"], q["seed"], q["mode"])
+        assert list(B) == list(Bp), i
+        for k in ("samples", "reached", "edges_scanned", "live_edges"):
+            assert st[k] == sp[k], (i, k)
+    for i in range(0, 30, 7):
+        q = qs[i]
+        Bo, calls, so = orc.greedy(t.n, t.row_ptr, t.col, t.prob, q["seeds"], q["b"], q["theta"],
+                                   q["seed"], q["mode"])
+        assert list(res[i][0]) == list(Bo), i
+        assert res[i][1]["samples"] == calls * q["theta"], i
+    with pytest.raises(gpu.IminError) as e:
+        srv.submit(t.seeds, 2, 100, 0, mode=7)
+    assert e.value.status == gpu.IMIN_EINVAL
+    srv.close()
+    g.close()
