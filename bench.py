@@ -428,8 +428,9 @@ def main() -> int:
     ap.add_argument("--pick-div", type=int, default=0)
     ap.add_argument("--pack-per-cu", type=int, default=0,
                     help="batched/served: packed-kernel workgroups per CU (-1: that kernel off)")
-    ap.add_argument("--graph", type=int, choices=[0, 1], default=0,
-                    help="batched workload: 1 captures each call's rounds into a HIP graph")
+    ap.add_argument("--graph", type=int, choices=[0, 1], default=1,
+                    help="batched workload: 1 (default) runs each call's rounds as one HIP graph, "
+                         "captured once per launch structure and replayed; 0 launches directly")
     ap.add_argument("--tune", action="store_true",
                     help="batched workload: tune the launch shape if no cached entry exists")
     args = ap.parse_args()

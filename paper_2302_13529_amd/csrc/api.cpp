@@ -261,6 +261,18 @@ void describe(imin_graph *g, int32_t nseeds, uint64_t seed, uint32_t theta)
     I.sample_base = 0;
 }
 
+// The vertices whose bit is set, ascending, appended to out (a word at a time).
+void append_set_bits(const std::vector<uint32_t> &bits, std::vector<int32_t> &out)
+{
+    for (size_t w = 0; w < bits.size(); ++w) {
+        uint32_t x = bits[w];
+        while (x) {
+            out.push_back((int32_t)(w * 32 + (size_t)__builtin_ctz(x)));
+            x &= x - 1;
+        }
+    }
+}
+
 int upload_call_state(imin_graph *g, const std::vector<int32_t> &seeds,
                       const std::vector<uint32_t> &inelig, uint64_t seed, uint32_t theta)
 {
@@ -297,8 +309,7 @@ int upload_call_state(imin_graph *g, const std::vector<int32_t> &seeds,
     }
     g->mask_known = false;
     g->masked.clear();
-    for (int32_t v = 0; v < g->n; ++v)
-        if ((inelig[v >> 5] >> (v & 31)) & 1u) g->masked.push_back(v);
+    append_set_bits(inelig, g->masked);
     if (!g->masked.empty() &&
         (!ok(hipMemcpyAsync(g->d_list + g->n, g->masked.data(), g->masked.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice, g->stream)) ||
@@ -383,6 +394,15 @@ int launch_large_on(imin_graph *g, const LargeTarget &t, uint32_t theta, uint64_
 
 void multi_free(MultiScratch &ms)
 {
+    if (ms.exec) (void)hipGraphExecDestroy(ms.exec);
+    ms.exec = nullptr;
+    ms.exec_key.clear();
+    dfree(ms.table);
+    dfree(ms.stages);
+    dfree(ms.stage);
+    dfree(ms.rounds);
+    dfree(ms.out);
+    ms.table_cap = ms.stages_cap = ms.stage_cap = ms.rounds_cap = ms.out_cap = 0;
     free_ws(ms.main_ws);
     free_ws(ms.big_ws);
     dfree(ms.ctrl);
@@ -778,12 +798,21 @@ struct StreamSwap {
     }
 };
 
+// A device buffer of at least `count` elements, kept and grown only when too small.
 template <class T>
-struct DeviceBuf {
-    T *p = nullptr;
-    ~DeviceBuf() { dfree(p); }
-    bool alloc(size_t count) { return ok(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T))); }
-};
+bool grow(T *&p, size_t &cap, size_t count)
+{
+    count = std::max<size_t>(count, 1);
+    if (p && cap >= count) return true;
+    dfree(p);
+    cap = 0;
+    if (!ok(hipMalloc(&p, count * sizeof(T)))) {
+        (void)hipGetLastError();
+        return false;
+    }
+    cap = count;
+    return true;
+}
 
 struct BatchItem {
     imin_instance *in = nullptr;
@@ -1280,8 +1309,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         if (g->mask_known) stage.insert(stage.end(), g->masked.begin(), g->masked.end());
         g->mask_known = false;
         g->masked.clear();
-        for (int32_t v = 0; v < g->n; ++v)
-            if ((it.inelig[(size_t)v >> 5] >> (v & 31)) & 1u) g->masked.push_back(v);
+        append_set_bits(it.inelig, g->masked);
         S.now = (int64_t)stage.size();
         S.nnow = (int32_t)g->masked.size();
         stage.insert(stage.end(), g->masked.begin(), g->masked.end());
@@ -1292,15 +1320,6 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         }
     }
     const int32_t stride = imin::kGatherB + std::max(max_nb, 1);
-    DeviceBuf<imin::InstanceDesc> d_table;
-    DeviceBuf<imin::BatchStage> d_stages;
-    DeviceBuf<int32_t> d_stage, d_rounds, d_out;
-    if (!d_table.alloc((size_t)count) || !d_stages.alloc((size_t)count) ||
-        !d_stage.alloc(stage.size()) || !d_rounds.alloc((size_t)count) ||
-        !d_out.alloc((size_t)count * stride)) {
-        (void)hipGetLastError();
-        return IMIN_ENOMEM;
-    }
     int64_t max_n = 0, max_m = 0;
     for (const BatchItem &it : items) {
         max_n = std::max<int64_t>(max_n, it.g->n);
@@ -1318,15 +1337,21 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
         multi_free(ms);
         return rc;
     }
-    if (!ok(hipMemcpyAsync(d_table.p, table.data(), table.size() * sizeof(imin::InstanceDesc),
+    if (!grow(ms.table, ms.table_cap, (size_t)count) ||
+        !grow(ms.stages, ms.stages_cap, (size_t)count) ||
+        !grow(ms.stage, ms.stage_cap, stage.size()) ||
+        !grow(ms.rounds, ms.rounds_cap, (size_t)count) ||
+        !grow(ms.out, ms.out_cap, (size_t)count * stride))
+        return IMIN_ENOMEM;
+    if (!ok(hipMemcpyAsync(ms.table, table.data(), table.size() * sizeof(imin::InstanceDesc),
                            hipMemcpyHostToDevice, bs)) ||
-        !ok(hipMemcpyAsync(d_stages.p, stages.data(), stages.size() * sizeof(imin::BatchStage),
+        !ok(hipMemcpyAsync(ms.stages, stages.data(), stages.size() * sizeof(imin::BatchStage),
                            hipMemcpyHostToDevice, bs)) ||
-        !ok(hipMemcpyAsync(d_stage.p, stage.data(), stage.size() * sizeof(int32_t),
+        !ok(hipMemcpyAsync(ms.stage, stage.data(), stage.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, bs)) ||
-        !ok(hipMemcpyAsync(d_rounds.p, rounds.data(), rounds.size() * sizeof(int32_t),
+        !ok(hipMemcpyAsync(ms.rounds, rounds.data(), rounds.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, bs)) ||
-        !ok(imin::launch_batch_setup(d_table.p, d_stages.p, d_stage.p, count, bs)))
+        !ok(imin::launch_batch_setup(ms.table, ms.stages, ms.stage, count, bs)))
         return IMIN_EDEVICE;
     // Rounds: every launch is queued at once; nothing waits for the host until the end
     // (GreedyReplace: one word read back per round, the count of runs that have ended).
@@ -1334,24 +1359,52 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
     if (!ok(imin::launch_fill_u32(ms.ctrl + 9, 1, 0, bs))) return IMIN_EDEVICE;
     if (shape.graph && !gr) {
         // One HIP graph of kernel nodes for all rounds (slots clear their own maps when
-        // their epochs wrap, so no memset is ever needed inside).
-        GraphCapture cap;
-        if (!ok(hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal))) return IMIN_EDEVICE;
-        cap.stream = bs;
-        int32_t act = count;
-        for (int32_t r = 0; r < max_rounds; ++r) {
-            while (act > 0 && items[(size_t)act - 1].rounds <= r) --act;
-            rc = multi_round(ms, d_table.p, act, prefix[(size_t)act], (uint32_t)r, shape,
-                             g0->num_cus, true, false, lt, bs);
-            if (rc) return rc;
+        // their epochs wrap, so no memset is ever needed inside). Every kernel reads the
+        // call's state through the device table, so the graph depends only on the launch
+        // structure below; a call with the same structure replays the kept graph.
+        std::vector<int64_t> key = {count, max_rounds, lt ? 1 : 0, g0->num_cus,
+                                    shape.waves_per_cu, shape.quad_limit, shape.pick_div,
+                                    shape.pack_per_cu, (int64_t)(uintptr_t)ms.table,
+                                    (int64_t)(uintptr_t)ms.ctrl, (int64_t)(uintptr_t)ms.pi,
+                                    (int64_t)(uintptr_t)ms.si, (int64_t)(uintptr_t)ms.oi,
+                                    (int64_t)(uintptr_t)ms.part_d, (int64_t)ms.cap,
+                                    (int64_t)(uintptr_t)ms.main_ws.map, ms.main_ws.slots,
+                                    ms.main_ws.n, ms.main_ws.lcap, ms.main_ws.xcap,
+                                    (int64_t)(uintptr_t)ms.big_ws.map, ms.big_ws.slots};
+        {
+            int32_t act = count;
+            for (int32_t r = 0; r < max_rounds; ++r) {
+                while (act > 0 && items[(size_t)act - 1].rounds <= r) --act;
+                key.push_back(act);
+                key.push_back(prefix[(size_t)act]);
+            }
         }
-        rc = cap.finish();
-        if (rc) return rc;
+        if (!ms.exec || ms.exec_key != key) {
+            if (ms.exec) (void)hipGraphExecDestroy(ms.exec);
+            ms.exec = nullptr;
+            ms.exec_key.clear();
+            GraphCapture cap;
+            if (!ok(hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal)))
+                return IMIN_EDEVICE;
+            cap.stream = bs;
+            int32_t act = count;
+            for (int32_t r = 0; r < max_rounds; ++r) {
+                while (act > 0 && items[(size_t)act - 1].rounds <= r) --act;
+                rc = multi_round(ms, ms.table, act, prefix[(size_t)act], (uint32_t)r, shape,
+                                 g0->num_cus, true, false, lt, bs);
+                if (rc) return rc;
+            }
+            rc = cap.finish();
+            if (rc) return rc;
+            ms.exec = cap.exec;  // kept with the scratch
+            cap.exec = nullptr;
+            ms.exec_key = std::move(key);
+        }
         hipEvent_t k0, k1;
         rc = kernel_events(g0, &k0, &k1);
         if (rc) return rc;
-        if (!ok(hipEventRecord(k0, bs)) || !ok(hipGraphLaunch(cap.exec, bs)) ||
-            !ok(hipEventRecord(k1, bs)) || !ok(hipStreamSynchronize(bs)))
+        if (!ok(hipEventRecord(k0, bs)) || !ok(hipGraphLaunch(ms.exec, bs)) ||
+            !ok(hipEventRecord(k1, bs)))
             return IMIN_EDEVICE;
     } else {
         int32_t active = count;
@@ -1361,7 +1414,7 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
             rc = kernel_events(g0, &k0, &k1);
             if (rc) return rc;
             if (!ok(hipEventRecord(k0, bs))) return IMIN_EDEVICE;
-            rc = multi_round(ms, d_table.p, active, prefix[(size_t)active], (uint32_t)r,
+            rc = multi_round(ms, ms.table, active, prefix[(size_t)active], (uint32_t)r,
                              shape, g0->num_cus, true, gr, lt, bs);
             if (rc) return rc;
             if (!ok(hipEventRecord(k1, bs))) return IMIN_EDEVICE;
@@ -1379,8 +1432,8 @@ int imin_greedy_batch(imin_instance *inst, int32_t count, int mode, const imin_l
     // Results: every graph's blocker slots, counters and error flag, gathered into one
     // buffer, then one copy and one wait.
     std::vector<int32_t> out((size_t)count * stride);
-    if (!ok(imin::launch_batch_gather(d_table.p, d_rounds.p, d_out.p, stride, count, bs)) ||
-        !ok(hipMemcpyAsync(out.data(), d_out.p, out.size() * sizeof(int32_t),
+    if (!ok(imin::launch_batch_gather(ms.table, ms.rounds, ms.out, stride, count, bs)) ||
+        !ok(hipMemcpyAsync(out.data(), ms.out, out.size() * sizeof(int32_t),
                            hipMemcpyDeviceToHost, bs)) ||
         !ok(hipEventRecord(g0->ev1, bs)) || !ok(hipEventSynchronize(g0->ev1)))
         return IMIN_EDEVICE;

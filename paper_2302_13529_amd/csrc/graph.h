@@ -141,6 +141,21 @@ struct MultiScratch {
     int32_t inst_cap = 0;                   // instances of the largest round
     unsigned long long *part_d = nullptr;   // inst_cap * kArgParts partial argmax results
     int32_t *part_i = nullptr;
+    // Batched calls: the instance table and call-state staging, kept across calls (grown on
+    // demand), and the HIP graph of the last captured call with the launch structure it was
+    // captured for (replayed while a call has the same structure).
+    InstanceDesc *table = nullptr;
+    size_t table_cap = 0;
+    BatchStage *stages = nullptr;
+    size_t stages_cap = 0;
+    int32_t *stage = nullptr;
+    size_t stage_cap = 0;
+    int32_t *rounds = nullptr;
+    size_t rounds_cap = 0;
+    int32_t *out = nullptr;
+    size_t out_cap = 0;
+    hipGraphExec_t exec = nullptr;
+    std::vector<int64_t> exec_key;
 };
 int multi_alloc(MultiScratch &ms, int num_cus, int64_t max_n, int64_t max_m, uint32_t cap,
                 int32_t max_inst, hipStream_t stream);

@@ -344,3 +344,30 @@ def test_batch_greedy_replace_equals_plain_and_oracle(gpu, batch16):
             assert st["samples"] == calls * th and st["reached"] == so["reached"], i
     for g in graphs:
         g.close()
+
+
+def test_captured_batch_replays_equal_direct_launches(gpu, batch16):
+    """The batched call's captured HIP graph is kept and replayed by later calls of the same
+    launch structure; the call state (keys, seeds) flows through the device table. Every
+    replay, with plain calls and direct batched calls in between, must equal the direct
+    launches of the same call."""
+    insts = batch16[:8]
+    graphs = [gpu.Graph(t.row_ptr, t.col, t.prob) for t in insts]
+    shape = dict(graph=1)
+    for rep in range(4):
+        # same budgets and theta every time (same structure), other keys and seed sets
+        probs = [(g.handle, t.seeds[: 1 + (rep + i) % len(t.seeds)], 4, 300, t.seed + 97 * rep)
+                 for i, (g, t) in enumerate(zip(graphs, insts))]
+        case(f"captured batch, call {rep}")
+        cap = gpu.imin_greedy_batch(probs, gpu.IMIN_AG, shape)
+        direct = gpu.imin_greedy_batch(probs, gpu.IMIN_AG, dict(graph=0))
+        for i, ((B, st), (Bd, sd)) in enumerate(zip(cap, direct)):
+            assert list(B) == list(Bd), (rep, i)
+            for k in ("samples", "reached", "edges_scanned", "live_edges"):
+                assert st[k] == sd[k], (rep, i, k)
+        # eager work on the same graphs between replays
+        g, t = graphs[rep], insts[rep]
+        Bp, _ = g.greedy(probs[rep][1], 4, 300, probs[rep][4], gpu.IMIN_AG)
+        assert list(Bp) == list(cap[rep][0])
+    for g in graphs:
+        g.close()
