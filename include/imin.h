@@ -83,7 +83,8 @@ typedef struct {
                                wave, or several per wave); the rest ran one workgroup per
                                sample */
     uint64_t pack_samples;  /* of those, samples finished by the kernel that runs several
-                               samples per wavefront (batched calls and the server) */
+                               samples per wavefront (batched calls and the server under
+                               the independent cascade model) */
 } imin_stats;
 
 /*
@@ -179,8 +180,10 @@ IMIN_API int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b,
  * automatic choice for that field). slots: concurrent samples, one workgroup each.
  * extra_cap: per-slot capacity for non-tree live edges; samples that exceed it are re-run
  * in large-capacity scratch. Results never depend on these values; they exist so tests can
- * check that, and to tune. Errors: IMIN_EINVAL for negative values or NULL g.
+ * check that, and to tune. Errors: IMIN_EINVAL for negative values or NULL g, IMIN_ERANGE
+ * for slots above IMIN_MAX_SLOTS.
  */
+#define IMIN_MAX_SLOTS 4096
 IMIN_API int imin_set_launch(imin_graph *g, int32_t slots, int64_t extra_cap);
 
 /*
@@ -204,7 +207,8 @@ typedef struct {
     int32_t pack_per_cu;  /* batched calls and the server: workgroups per compute unit of the
                              kernel that runs several small samples per wavefront (0: the
                              default, 2; -1: that kernel off, every sample starts in the
-                             one-sample-per-wave kernel) */
+                             one-sample-per-wave kernel). With it on, its hand-overs go to
+                             the workgroup kernel and the other fields have no effect */
 } imin_launch;
 
 /*
@@ -254,8 +258,8 @@ typedef struct {
  * imin_graph_destroy releases it.
  *   mode    IMIN_AG or IMIN_GR, for every instance.
  *   count   >= 1; the total of theta over the batch must not exceed 2^31 (IMIN_ERANGE).
- *   launch  the wave kernel's launch shape (NULL: defaults); the graphs' own imin_set_small
- *           settings do not apply here.
+ *   launch  the wavefront-level kernels' launch shape (NULL: defaults); the graphs' own
+ *           imin_set_small settings do not apply here.
  * Errors: IMIN_EINVAL (any instance invalid as for imin_greedy, a graph repeated, graphs of
  * different models, NULL inst, negative launch values), IMIN_ERANGE, IMIN_ENOMEM,
  * IMIN_EDEVICE.

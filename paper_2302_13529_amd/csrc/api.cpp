@@ -57,13 +57,14 @@ void free_ws(Workspace &ws)
     dfree(ws.extra);
     dfree(ws.rng);
     dfree(ws.epoch);
+    dfree(ws.dirty);
     ws = Workspace();
 }
 
 size_t slot_bytes(int64_t n, int64_t lcap, int64_t xcap, bool rng = false)
 {
     return (size_t)n * sizeof(unsigned long long) + (size_t)lcap * sizeof(imin::LocalVtx) +
-           (size_t)(lcap + 1) * sizeof(int32_t) + (size_t)xcap * sizeof(int2) + sizeof(uint32_t) +
+           (size_t)(lcap + 1) * sizeof(int32_t) + (size_t)xcap * sizeof(int2) + 2 * sizeof(uint32_t) +
            (rng ? (size_t)lcap * sizeof(int2) : 0);
 }
 
@@ -84,14 +85,16 @@ int alloc_ws(Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap
                 ok(hipMalloc(&ws.lvl, S * (size_t)(lcap + 1) * sizeof(int32_t))) &&
                 ok(hipMalloc(&ws.extra, S * (size_t)std::max<int64_t>(xcap, 1) * sizeof(int2))) &&
                 (!rng || ok(hipMalloc(&ws.rng, S * (size_t)lcap * sizeof(int2)))) &&
-                ok(hipMalloc(&ws.epoch, S * sizeof(uint32_t)));
+                ok(hipMalloc(&ws.epoch, S * sizeof(uint32_t))) &&
+                ok(hipMalloc(&ws.dirty, S * sizeof(uint32_t)));
     if (!good) {
         free_ws(ws);
         (void)hipGetLastError();
         return IMIN_ENOMEM;
     }
     if (!ok(hipMemsetAsync(ws.map, 0, S * (size_t)n * sizeof(unsigned long long), stream)) ||
-        !ok(hipMemsetAsync(ws.epoch, 0, S * sizeof(uint32_t), stream))) {
+        !ok(hipMemsetAsync(ws.epoch, 0, S * sizeof(uint32_t), stream)) ||
+        !ok(hipMemsetAsync(ws.dirty, 0, S * sizeof(uint32_t), stream))) {
         free_ws(ws);
         return IMIN_EDEVICE;
     }
@@ -517,7 +520,11 @@ int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst,
         return IMIN_EDEVICE;
     // The smallest samples first, several to a wavefront (independent cascade only: the
     // packed kernel keeps the seed level's edge coins in registers); what outgrows it goes
-    // to the one-sample-per-wave kernel through a device-side list.
+    // straight to the workgroup kernel through a device-side list. The hand-overs are the
+    // few larger samples (over 63 vertices or 64 extra edges), which the workgroup kernel's
+    // 1024 slots finish sooner than one wavefront each would. Without the packed kernel
+    // (linear threshold, or switched off) the one-sample-per-wave kernel takes every sample
+    // first and hands its overflow on.
     const bool pack = !lt && shape.pack_per_cu >= 0;
     if (pack) {
         imin::PackArgs p;
@@ -537,11 +544,6 @@ int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst,
     }
     imin::SmallArgs s;
     std::memset(&s, 0, sizeof(s));
-    if (pack) {
-        s.in_inst = ms.pi;
-        s.in_j = ms.pj;
-        s.in_count = ms.ctrl + 7;
-    }
     s.inst = inst;
     s.ninst = ninst;
     s.total = total;
@@ -553,14 +555,14 @@ int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst,
     s.spill_j = ms.sj;
     s.spill_count = ms.ctrl + 1;
     s.error = ms.ctrl + 2;
-    if (!ok(imin::launch_decrease_small(s, small_grid(num_cus, shape), stream)))
+    if (!pack && !ok(imin::launch_decrease_small(s, small_grid(num_cus, shape), stream)))
         return IMIN_EDEVICE;
     DecreaseArgs a;
     std::memset(&a, 0, sizeof(a));
     a.n = (int32_t)ms.n;
     a.theta = total;
-    a.sample_list = ms.sj;
-    a.sample_count = ms.ctrl + 1;
+    a.sample_list = pack ? ms.pj : ms.sj;
+    a.sample_count = pack ? ms.ctrl + 7 : ms.ctrl + 1;
     a.next = ms.ctrl + 3;
     a.ovf_list = ms.oj;
     a.ovf_count = ms.ctrl + 5;
@@ -568,7 +570,7 @@ int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst,
     a.spill_ok = spill ? 1 : 0;
     a.ws = ms.main_ws;
     a.inst = inst;
-    a.sample_inst = ms.si;
+    a.sample_inst = pack ? ms.pi : ms.si;
     a.ovf_inst = ms.oi;
     a.round = round;
     a.lt = lt ? 1 : 0;
@@ -1027,6 +1029,7 @@ void imin_graph_destroy(imin_graph *g) { destroy(g); }
 int imin_set_launch(imin_graph *g, int32_t slots, int64_t extra_cap)
 {
     if (!g || slots < 0 || extra_cap < 0) return IMIN_EINVAL;
+    if (slots > IMIN_MAX_SLOTS) return IMIN_ERANGE;
     g->force_slots = slots;
     g->force_xcap = extra_cap;
     return IMIN_OK;

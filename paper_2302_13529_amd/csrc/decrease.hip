@@ -108,11 +108,14 @@ struct Shared {
 // kept as an extra edge (edges from the merged seed never matter for dominators: their
 // targets are its children). tag = this sample's epoch << lbits: every map entry written in
 // this sample is at least tag, every older one below it.
+// inc: 1 when the slot keeps reach counts in its map (the count word of w gains this
+// sample's reach), else 0.
 // kRng: w's row range is read beside the claim, so that the next level starts from it
 // without a dependent row_ptr read.
 template <bool kRng, class Sh>
 __device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv, Sh &sh, int w,
-                                      int src, uint32_t tag, const int32_t *row_ptr)
+                                      int src, uint32_t tag, uint32_t inc,
+                                      const int32_t *row_ptr)
 {
     int2 r = make_int2(0, 0);
     if (kRng) r = make_int2(row_ptr[w], row_ptr[w + 1]);
@@ -124,7 +127,7 @@ __device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv,
         if (id < a.ws.lcap) {
             // a later max with tag64 leaves this larger value in place; the count word
             // (low) gains this sample's reach
-            const uint32_t cnt = (uint32_t)old + (a.count_reach ? 1u : 0u);
+            const uint32_t cnt = (uint32_t)old + inc;
             __hip_atomic_store(&sv.map[w],
                                ((unsigned long long)(tag | (uint32_t)(id + 1)) << 32) | cnt,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -165,14 +168,15 @@ __device__ __forceinline__ void locate(const Sh &sh, int cnt, int q, int &l, int
 template <bool kRng, class Sh>
 __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView &sv, Sh &sh,
                                            uint32_t mask, uint4 col, int src, uint32_t tag,
-                                           uint32_t &live, const int32_t *row_ptr)
+                                           uint32_t inc, uint32_t &live,
+                                           const int32_t *row_ptr)
 {
     live += (uint32_t)__builtin_popcount(mask);
     while (mask) {
         const int i = __builtin_ctz(mask);
         mask &= mask - 1;
         const uint32_t c = i == 0 ? col.x : i == 1 ? col.y : i == 2 ? col.z : col.w;
-        visit<kRng>(a, sv, sh, (int)c, src, tag, row_ptr);
+        visit<kRng>(a, sv, sh, (int)c, src, tag, inc, row_ptr);
     }
 }
 
@@ -185,7 +189,7 @@ __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView
 template <int B, bool kLT, bool kRng>
 __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv, Shared<B> &sh,
                        bool from_seeds, int lo, int hi, uint32_t j, uint32_t tag,
-                       uint32_t &scanned, uint32_t &live)
+                       uint32_t inc, uint32_t &scanned, uint32_t &live)
 {
     constexpr int kChunk = Shared<B>::kChunk;
     const int tid = threadIdx.x;
@@ -256,8 +260,10 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
                 if (m1) c1 = c.col4[quad1];
                 if (m2) c2 = c.col4[quad2];
             }
-            visit_mask<kRng>(a, sv, sh, m1, c1, from_seeds ? 0 : base + l1, tag, live, c.row_ptr);
-            visit_mask<kRng>(a, sv, sh, m2, c2, from_seeds ? 0 : base + l2, tag, live, c.row_ptr);
+            visit_mask<kRng>(a, sv, sh, m1, c1, from_seeds ? 0 : base + l1, tag, inc, live,
+                             c.row_ptr);
+            visit_mask<kRng>(a, sv, sh, m2, c2, from_seeds ? 0 : base + l2, tag, inc, live,
+                             c.row_ptr);
         }
         __syncthreads();
     }
@@ -298,6 +304,13 @@ void decrease_kernel(DecreaseArgs a)
     uint32_t epoch = a.ws.epoch[slot];
     const uint32_t emax = 0xFFFFFFFFu >> a.ws.lbits;  // largest epoch the map entries hold
     const uint32_t count = a.sample_list ? *a.sample_count : a.theta;
+    // Reach counts in the map: every reached vertex's 1 rides on its claim, and
+    // launch_flush_counts later adds the slot's whole map into D, n entries per slot. A slot
+    // takes that route after its first sample when the samples it can expect to run
+    // (count / slots of them, each about that size) reach at least n/4 vertices in all;
+    // below that the flush would cost more than the D atomics it saves.
+    const uint32_t per_slot = count / gridDim.x;
+    bool cnt_on = false;
 
     for (;;) {
         if (tid == 0) sh.idx = atomicAdd(a.next, 1u);
@@ -345,14 +358,15 @@ void decrease_kernel(DecreaseArgs a)
         __syncthreads();
 
         uint32_t p_scanned = 0, p_live = 0;
-        expand<B, kLT, kMulti>(a, c, sv, sh, true, 0, c.nseeds, j, tag, p_scanned, p_live);
+        const uint32_t inc = cnt_on ? 1u : 0u;
+        expand<B, kLT, kMulti>(a, c, sv, sh, true, 0, c.nseeds, j, tag, inc, p_scanned, p_live);
         int L = 1, lo = 1;
         int hi = sh.tail;
         __syncthreads();
         while (lo < hi) {
             if (sh.ovf) break;
             if (tid == 0) sv.lvl[L + 1] = hi;
-            expand<B, kLT, kMulti>(a, c, sv, sh, false, lo, hi, j, tag, p_scanned, p_live);
+            expand<B, kLT, kMulti>(a, c, sv, sh, false, lo, hi, j, tag, inc, p_scanned, p_live);
             lo = hi;
             hi = sh.tail;
             ++L;
@@ -360,7 +374,7 @@ void decrease_kernel(DecreaseArgs a)
         }
         if (sh.ovf) {
             // the sample is re-run elsewhere: take back the reach counts of its claims
-            if (a.count_reach) {
+            if (cnt_on) {
                 const int nv = min(sh.tail, (int)a.ws.lcap);
                 for (int i = 1 + tid; i < nv; i += B)
                     __hip_atomic_fetch_sub(reinterpret_cast<uint32_t *>(&sv.map[sv.loc[i].glob]),
@@ -470,7 +484,7 @@ void decrease_kernel(DecreaseArgs a)
                     __hip_atomic_fetch_add(&sv.loc[r.tdom].csz, r.csz, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
                 // with reach counts in the map, a leaf of the dominator tree adds nothing here
-                const int add = a.count_reach ? r.csz - 1 : r.csz;
+                const int add = cnt_on ? r.csz - 1 : r.csz;
                 if (add > 0) atomicAdd(&c.D[r.glob], (unsigned long long)add);
             }
             __syncthreads();
@@ -481,38 +495,72 @@ void decrease_kernel(DecreaseArgs a)
             atomicAdd(&c.stats[2], (unsigned long long)sh.scanned);
             atomicAdd(&c.stats[3], (unsigned long long)sh.live);
         }
+        if (a.count_reach && !cnt_on &&
+            (unsigned long long)(nV - 1) * per_slot >= (unsigned long long)a.ws.n / 4)
+            cnt_on = true;
     }
-    if (tid == 0) a.ws.epoch[slot] = epoch;
+    if (tid == 0) {
+        a.ws.epoch[slot] = epoch;
+        if (a.count_reach) a.ws.dirty[slot] = cnt_on ? 1u : 0u;
+    }
 }
 
-// D[v] += the reach counts of v in a group of kFlushSlots slots (blockIdx.y), which go back
-// to 0. A thread owns v within its group and has all the group's loads in flight at once;
-// for each slot the threads of a wave read consecutive entries.
+// D[v] += the reach counts of v in every slot that kept them (dirty), which go back to 0.
+// Work items are (group of kFlushSlots slots, range of kFlushSpan vertices); a persistent
+// grid walks them. Each workgroup first gathers the flags of all slots into LDS with one
+// round of loads, so a launch in which no slot kept counts ends after that round. A thread
+// owns one vertex of the range and has all its group's loads in flight at once; for each
+// slot the threads of a wave read consecutive entries.
 constexpr int kFlushSlots = 16;
+constexpr int kFlushBlock = 256;
+constexpr int kFlushSpan = 4 * kFlushBlock;
+constexpr int kFlushGrid = 2048;
+constexpr int kFlushMaxGroups = 256;  // slots <= 4096
 
-__global__ void flush_counts_kernel(unsigned long long *map, int32_t slots, int64_t n,
-                                    unsigned long long *D)
+__global__ __launch_bounds__(kFlushBlock) void flush_counts_kernel(
+    unsigned long long *map, const uint32_t *dirty, int32_t slots, int64_t n,
+    unsigned long long *D)
 {
-    const int32_t s0 = blockIdx.y * kFlushSlots;
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t k[kFlushSlots];
-#pragma unroll
-        for (int i = 0; i < kFlushSlots; ++i)
-            k[i] = s0 + i < slots
-                       ? reinterpret_cast<const uint32_t *>(
-                             &map[(size_t)(s0 + i) * (size_t)n + (size_t)v])[0]
-                       : 0u;
-        unsigned long long sum = 0;
-#pragma unroll
-        for (int i = 0; i < kFlushSlots; ++i) {
-            if (k[i]) {
-                sum += k[i];
-                reinterpret_cast<uint32_t *>(&map[(size_t)(s0 + i) * (size_t)n + (size_t)v])[0] =
-                    0u;
-            }
+    __shared__ uint32_t gon[kFlushMaxGroups];
+    __shared__ int any;
+    const int32_t groups = (slots + kFlushSlots - 1) / kFlushSlots;
+    for (int i = threadIdx.x; i < groups; i += kFlushBlock) gon[i] = 0;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int s = threadIdx.x; s < slots; s += kFlushBlock)
+        if (dirty[s]) {
+            atomicOr(&gon[s / kFlushSlots], 1u << (s % kFlushSlots));
+            any = 1;
         }
-        if (sum) atomicAdd(&D[v], sum);
+    __syncthreads();
+    if (!any) return;
+    const int64_t spans = (n + kFlushSpan - 1) / kFlushSpan;
+    for (int64_t item = blockIdx.x; item < spans * groups; item += gridDim.x) {
+        const int32_t g = (int32_t)(item / spans);
+        const uint32_t on = gon[g];
+        if (!on) continue;
+        const int32_t s0 = g * kFlushSlots;
+        const int64_t v0 = (item - (int64_t)g * spans) * kFlushSpan;
+        const int64_t v1 = min<int64_t>(v0 + kFlushSpan, n);
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += kFlushBlock) {
+            uint32_t k[kFlushSlots];
+#pragma unroll
+            for (int i = 0; i < kFlushSlots; ++i)
+                k[i] = (on >> i) & 1u
+                           ? reinterpret_cast<const uint32_t *>(
+                                 &map[(size_t)(s0 + i) * (size_t)n + (size_t)v])[0]
+                           : 0u;
+            unsigned long long sum = 0;
+#pragma unroll
+            for (int i = 0; i < kFlushSlots; ++i) {
+                if (k[i]) {
+                    sum += k[i];
+                    reinterpret_cast<uint32_t *>(
+                        &map[(size_t)(s0 + i) * (size_t)n + (size_t)v])[0] = 0u;
+                }
+            }
+            if (sum) atomicAdd(&D[v], sum);
+        }
     }
 }
 
@@ -522,10 +570,12 @@ hipError_t launch_flush_counts(const Workspace &ws, int32_t slots, unsigned long
                                hipStream_t stream)
 {
     if (slots <= 0 || ws.n <= 0) return hipSuccess;
-    const int64_t blocks = std::min<int64_t>(4096, (ws.n + 255) / 256);
-    const int groups = (slots + kFlushSlots - 1) / kFlushSlots;
-    hipLaunchKernelGGL(flush_counts_kernel, dim3((unsigned)blocks, (unsigned)groups), dim3(256), 0,
-                       stream, ws.map, slots, ws.n, D);
+    if (slots > kFlushSlots * kFlushMaxGroups) return hipErrorInvalidValue;
+    const int64_t items = ((ws.n + kFlushSpan - 1) / kFlushSpan) *
+                          ((slots + kFlushSlots - 1) / kFlushSlots);
+    const int grid = (int)std::min<int64_t>(kFlushGrid, items);
+    hipLaunchKernelGGL(flush_counts_kernel, dim3(grid), dim3(kFlushBlock), 0, stream, ws.map,
+                       ws.dirty, slots, ws.n, D);
     return hipGetLastError();
 }
 

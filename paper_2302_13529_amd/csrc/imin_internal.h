@@ -60,6 +60,8 @@ struct Workspace {
     int2 *rng = nullptr;       // slots * lcap, many-instance workspaces only: the row range
                                // (row_ptr pair) of each local vertex, read when it is claimed
     uint32_t *epoch = nullptr; // slots: epoch of the slot's last sample
+    uint32_t *dirty = nullptr; // slots: 1 when the slot's last counting launch left reach
+                               // counts in its map (launch_flush_counts reads only those)
     size_t bytes = 0;
 };
 
@@ -88,8 +90,10 @@ struct DecreaseArgs {
     uint32_t *error;         // set when a sample overflows with spill_ok == 0
     int32_t spill_ok;
     int32_t reach_only;      // count reached vertices only (spread estimates)
-    int32_t count_reach;     // add each reached vertex's 1 into its slot's map entry (the
-                             // caller folds them into D with launch_flush_counts)
+    int32_t count_reach;     // a slot may add each reached vertex's 1 into its map entry
+                             // instead of D (the caller folds them into D with
+                             // launch_flush_counts); each slot decides after its first
+                             // sample and records the choice in ws.dirty
     Workspace ws;            // slot maps of `n` entries
     // Many-instance launches (inst non-null): sample idx is sample sample_list[idx] of
     // instance inst[sample_inst[idx]] with key seed + round; overflowing samples are
@@ -160,11 +164,6 @@ struct SmallArgs {
     const InstanceDesc *inst; // ascending sample_base
     int32_t ninst;
     uint32_t total;           // samples of the launch: sum of the instances' theta
-    // When in_j is non-null the launch works on the list of *in_count samples handed over
-    // by the packed kernel instead: sample idx is sample in_j[idx] of instance in_inst[idx].
-    const uint32_t *in_inst;
-    const uint32_t *in_j;
-    const uint32_t *in_count;
     uint32_t round;           // added to every instance's seed to form the key
     int32_t quad_limit;       // a frontier chunk with more edge quads goes to the large kernel
     int32_t pick_div;         // runs of samples: about remaining / (pick_div * waves)
@@ -197,7 +196,7 @@ struct PackArgs {
     int32_t quad_limit;       // a frontier vertex with more edge quads is handed over
     int32_t pick_div;         // runs of samples: about remaining / (pick_div * waves)
     uint32_t *next;           // work counter
-    uint32_t *out_inst;       // samples handed to the wave kernel: instance, sample index
+    uint32_t *out_inst;       // samples handed to the workgroup kernel: instance, sample
     uint32_t *out_j;
     uint32_t *out_count;
     uint32_t *error;          // bit 2: dominator iteration did not settle (never expected)

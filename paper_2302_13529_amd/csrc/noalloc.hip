@@ -109,6 +109,7 @@ bool carve_ws(Carve &c, imin::Workspace &ws, int64_t n, int32_t slots, int64_t l
     ws.lvl = c.take<int32_t>(S * (size_t)(lcap + 1));
     ws.extra = c.take<int2>(S * (size_t)std::max<int64_t>(xcap, 1));
     ws.epoch = c.take<uint32_t>(S);
+    ws.dirty = c.take<uint32_t>(S);
     ws.rng = nullptr;
     ws.slots = slots;
     ws.n = n;
@@ -158,7 +159,7 @@ int imin_decrease_noalloc(imin_graph *g, const int32_t *S, int32_t nS, const uin
     Carve probe{base, fixed};
     imin::Workspace one;
     if (!carve_ws(probe, one, n, 1, lcap, xcap)) return IMIN_ERANGE;
-    const size_t per_slot = probe.used - fixed + 5 * 256;
+    const size_t per_slot = probe.used - fixed + 6 * 256;
     const int32_t slots = (int32_t)std::max<size_t>(
         1, std::min<size_t>((size_t)imin::kSlotsPerCu * g->num_cus,
                             (kScratchBytes - fixed) / per_slot));
@@ -212,7 +213,8 @@ int imin_decrease_noalloc(imin_graph *g, const int32_t *S, int32_t nS, const uin
         if (w->slots <= 0) continue;
         if (!ok(imin::launch_fill_u32(reinterpret_cast<uint32_t *>(w->map),
                                       2 * (int64_t)w->slots * w->n, 0u, st)) ||
-            !ok(imin::launch_fill_u32(w->epoch, w->slots, 0u, st)))
+            !ok(imin::launch_fill_u32(w->epoch, w->slots, 0u, st)) ||
+            !ok(imin::launch_fill_u32(w->dirty, w->slots, 0u, st)))
             return IMIN_EDEVICE;
     }
     if (!ok(imin::launch_fill_u64(reinterpret_cast<unsigned long long *>(d_counts), n, 0ull, st)) ||

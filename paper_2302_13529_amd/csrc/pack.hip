@@ -21,8 +21,8 @@
 //     Theorem 6).
 // A sample that reaches kPackV - 1 vertices, keeps more than kPackX extra edges, or expands a
 // vertex with more edge quads than the quad limit is abandoned (nothing accumulated, its
-// counters dropped) and listed for the one-sample-per-wave kernel; results never depend on
-// which kernel finished a sample.
+// counters dropped) and listed for the workgroup kernel; results never depend on which
+// kernel finished a sample.
 #include "imin_internal.h"
 #include "philox.h"
 #include "wave.h"

@@ -345,9 +345,7 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
     sc.total = -1;
     Tally tally{0, 0, 0, 0};
     const uint32_t nwaves = gridDim.x * kSW;
-    // list mode: the samples the packed kernel handed over (that launch has finished)
-    const bool listed = a.in_j != nullptr;
-    const uint32_t total = listed ? *a.in_count : a.total;
+    const uint32_t total = a.total;
     for (;;) {
         // Guided self-scheduling: runs of consecutive samples (one instance, one seed cache)
         // that shrink as the launch drains, so the waves finish together.
@@ -366,11 +364,7 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
         const uint32_t last = min(first + want, total);
         for (uint32_t idx = first; idx < last; ++idx) {
             int want_inst = cur;
-            uint32_t j = 0;
-            if (listed) {
-                want_inst = (int)__builtin_amdgcn_readfirstlane(a.in_inst[idx]);
-                j = __builtin_amdgcn_readfirstlane(a.in_j[idx]);
-            } else if (cur < 0 || idx < cur_lo || idx >= cur_hi) {
+            if (cur < 0 || idx < cur_lo || idx >= cur_hi) {
                 // the last instance whose first sample index is <= idx
                 int lo = 0, hi = a.ninst - 1;
                 while (lo < hi) {
@@ -398,21 +392,19 @@ __global__ __launch_bounds__(kSmallBlock) void decrease_small_kernel(SmallArgs a
                            &I.ctrl[kCtrlDone], __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT)) != 0u;
                 if (done) skip = true;
-                // LT: vertex-keyed choices, no quad cache; listed samples come in no
-                // particular instance order, so they read the seed rows from memory
-                if (kLT || skip || listed) sc.total = -1;
+                // LT: vertex-keyed choices, no quad cache
+                if (kLT || skip) sc.total = -1;
                 else build_seed_cache(I, ws.e0, ws.e1, ws.ex, sc);
             }
-            if (!listed) j = idx - cur_lo;
+            const uint32_t j = idx - cur_lo;
             if (done) {
-                // dropped: the rest of the run within this instance (list mode: this one)
-                idx += (listed ? 1u : min(last, cur_hi) - idx) - 1;
+                // dropped: the rest of the run within this instance
+                idx += min(last, cur_hi) - idx - 1;
                 continue;
             }
             if (skip) {
-                // the rest of the run within this instance, listed at once (list mode:
-                // this one sample)
-                const uint32_t cnt = listed ? 1u : min(last, cur_hi) - idx;
+                // the rest of the run within this instance, listed at once
+                const uint32_t cnt = min(last, cur_hi) - idx;
                 uint32_t pos = 0;
                 if (lane == 0) pos = atomicAdd(a.spill_count, cnt);
                 pos = __builtin_amdgcn_readfirstlane(__shfl(pos, 0, 64));

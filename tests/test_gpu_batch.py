@@ -106,11 +106,15 @@ def test_batch_equals_plain_and_oracle(gpu, batch16):
         assert st["live_edges"] == so["live_edges"], i
         Bp, sp = g.greedy(t.seeds, b, th, t.seed, gpu.IMIN_AG)
         assert list(Bp) == list(B), i
-    for wpc, ql, pd, gr in ((4, 0, 0, 0), (8, 1, 1, 0), (32, 64, 16, 0), (0, 0, 0, 1),
-                            (8, 1, 2, 1), (0, 0, 0, 1)):
-        case(f"batched AG, waves_per_cu={wpc} quad_limit={ql} pick_div={pd} graph={gr}")
+    # the wave kernel's shape matters with the packed kernel off (pack_per_cu -1)
+    for wpc, ql, pd, gr, ppc in ((4, 0, 0, 0, -1), (8, 1, 1, 0, -1), (32, 64, 16, 0, -1),
+                                 (0, 0, 0, 1, 0), (8, 1, 2, 1, -1), (0, 0, 0, 1, 0),
+                                 (0, 0, 1, 0, 1), (0, 0, 16, 0, 8)):
+        case(f"batched AG, waves_per_cu={wpc} quad_limit={ql} pick_div={pd} graph={gr} "
+             f"pack_per_cu={ppc}")
         res2 = gpu.imin_greedy_batch(probs, gpu.IMIN_AG,
-                                     dict(waves_per_cu=wpc, quad_limit=ql, pick_div=pd, graph=gr))
+                                     dict(waves_per_cu=wpc, quad_limit=ql, pick_div=pd, graph=gr,
+                                          pack_per_cu=ppc))
         for (B, st), (B2, st2) in zip(res, res2):
             assert list(B) == list(B2)
             assert st["reached"] == st2["reached"] and st["live_edges"] == st2["live_edges"]

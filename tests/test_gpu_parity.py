@@ -256,7 +256,13 @@ def test_errors_leave_outputs_untouched(gpu, tiny):
         g.greedy(t.seeds, -1, 10, 0, gpu.IMIN_AG)
     with pytest.raises(gpu.IminError):
         g.greedy(t.seeds, 2, 10, 0, 7)
-    # the handle still works afterwards
+    with pytest.raises(gpu.IminError) as e:
+        g.set_launch(4097, 0)
+    assert e.value.status == gpu.IMIN_ERANGE
+    # the handle still works afterwards (4096 slots are allowed)
+    g.set_launch(4096, 0)
+    check_decrease(g, t.n, t.row_ptr, t.col, t.prob, t.seeds, None, 5000, 2, "4096 slots")
+    g.set_launch(0, 0)
     check_decrease(g, t.n, t.row_ptr, t.col, t.prob, t.seeds, None, 50, 1, "after-errors")
     g.close()
 
