@@ -353,8 +353,9 @@ IMIN_API int imin_server_result(imin_server *s, uint64_t ticket, int32_t *blocke
  *             (written only by the kernels; its contents are undefined if the call fails).
  *   stats     optional host struct, as for imin_decrease (device_ms and kernel_ms are both
  *             the whole call).
- * Limits: the graph's scratch must fit the array -- per workgroup slot about 28 * (n + 1)
- * bytes plus 2 * n, plus two large-capacity slots of about 28 * n + 8 * m bytes when a slot's
+ * Limits: the graph's scratch must fit the array -- per workgroup slot about 30 * (n + 1)
+ * bytes (38 * (n + 1) under IC, whose slots also keep each reached vertex's row range),
+ * plus two large-capacity slots of about that much plus 8 * m bytes when a slot's
  * extra-edge list cannot hold m edges, plus 8 * theta + 9 * n bytes of lists and marks --
  * else IMIN_ERANGE (for example a 2^17-vertex, 10^6-edge graph fits; a 2^22-vertex one does
  * not). Fewer slots than imin_decrease uses may fit, which costs speed, never results.

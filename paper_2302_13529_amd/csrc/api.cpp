@@ -125,7 +125,7 @@ int size_workspaces(imin_graph *g, int32_t max_slots)
         size_t free_b = 0, total_b = 0;
         if (!ok(hipMemGetInfo(&free_b, &total_b))) return IMIN_EDEVICE;
         free_b += g->main_ws.bytes;  // the current allocation is released before a new one
-        const size_t per = slot_bytes(g->n, lcap, xcap);
+        const size_t per = slot_bytes(g->n, lcap, xcap, g->model == IMIN_IC);
         const size_t by_mem = std::max<size_t>(1, (free_b / 2) / per);
         slots = (int32_t)std::min<size_t>((size_t)imin::kSlotsPerCu * g->num_cus, by_mem);
         if (max_slots > 0) slots = std::min(slots, max_slots);
@@ -136,10 +136,12 @@ int size_workspaces(imin_graph *g, int32_t max_slots)
             (have >= slots || (max_slots == 0 && have > kSmallModeSlots)))
             slots = have;
     }
-    int rc = alloc_ws(g->main_ws, g->n, slots, lcap, xcap, g->stream, false);
+    // independent cascade: slots keep each claimed vertex's row range (from its edge record)
+    const bool rng = g->model == IMIN_IC;
+    int rc = alloc_ws(g->main_ws, g->n, slots, lcap, xcap, g->stream, rng);
     if (rc) return rc;
     if (xcap < xmax) {
-        rc = alloc_ws(g->big_ws, g->n, kSpillSlots, lcap, xmax, g->stream, false);
+        rc = alloc_ws(g->big_ws, g->n, kSpillSlots, lcap, xmax, g->stream, rng);
         if (rc) return rc;
     } else {
         free_ws(g->big_ws);
@@ -357,6 +359,7 @@ int launch_large_on(imin_graph *g, const LargeTarget &t, uint32_t theta, uint64_
     std::memset(&a, 0, sizeof(a));
     a.row_ptr = g->d_row_ptr;
     a.col4 = g->d_col4;
+    a.edge = g->d_edge;
     a.thr4 = t.thr4;
     a.lo4 = g->d_lo4;
     a.lt = g->model == IMIN_LT ? 1 : 0;
@@ -758,6 +761,7 @@ void destroy(imin_graph *g)
     free_ws(g->big_ws);
     dfree(g->d_row_ptr);
     dfree(g->d_col4);
+    dfree(g->d_edge);
     dfree(g->d_thr4);
     dfree(g->d_thr_orig);
     dfree(g->d_lo4);
@@ -997,7 +1001,8 @@ int imin_graph_create_model(int32_t n, int32_t m, const int32_t *row_ptr, const 
         ok(hipMalloc(&g->d_part_d, (size_t)g->parts * sizeof(unsigned long long))) &&
         ok(hipMalloc(&g->d_part_i, (size_t)g->parts * sizeof(int32_t))) &&
         ok(hipMalloc(&g->d_x, sizeof(int32_t))) &&
-        (model != IMIN_LT || ok(hipMalloc(&g->d_lo4, hlo.size() * sizeof(uint32_t))));
+        (model != IMIN_LT || ok(hipMalloc(&g->d_lo4, hlo.size() * sizeof(uint32_t)))) &&
+        (model != IMIN_IC || ok(hipMalloc(&g->d_edge, hcol.size() * sizeof(uint4))));
     if (!good) {
         (void)hipGetLastError();
         destroy(g);
@@ -1019,6 +1024,26 @@ int imin_graph_create_model(int32_t n, int32_t m, const int32_t *row_ptr, const 
                                            hipMemcpyHostToDevice)))) {
         destroy(g);
         return IMIN_EDEVICE;
+    }
+    if (model == IMIN_IC) {
+        // edge records: padding slots past m stay zero (their coins are never live)
+        std::vector<uint4> hedge;
+        try {
+            hedge.assign(hcol.size(), make_uint4(0, 0, 0, 0));
+        } catch (...) {
+            destroy(g);
+            return IMIN_ENOMEM;
+        }
+        for (int64_t e = 0; e < (int64_t)m; ++e) {
+            const int32_t v = col[e];
+            hedge[(size_t)e] = make_uint4((uint32_t)v, (uint32_t)row_ptr[v],
+                                          (uint32_t)row_ptr[(size_t)v + 1], 0u);
+        }
+        if (!ok(hipMemcpy(g->d_edge, hedge.data(), hedge.size() * sizeof(uint4),
+                          hipMemcpyHostToDevice))) {
+            destroy(g);
+            return IMIN_EDEVICE;
+        }
     }
     *out = g;
     return IMIN_OK;

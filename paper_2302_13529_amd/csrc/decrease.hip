@@ -78,7 +78,7 @@ struct Call {
 };
 
 struct SlotView {
-    int2 *rng;  // many-instance launches: row range of each local vertex
+    int2 *rng;  // row range of each local vertex (none in linear-threshold single calls)
     unsigned long long *map;
     LocalVtx *loc;
     int32_t *lvl;
@@ -110,15 +110,12 @@ struct Shared {
 // this sample is at least tag, every older one below it.
 // inc: 1 when the slot keeps reach counts in its map (the count word of w gains this
 // sample's reach), else 0.
-// kRng: w's row range is read beside the claim, so that the next level starts from it
+// kRng: w's row range r is kept with its local id, so that the next level starts from it
 // without a dependent row_ptr read.
 template <bool kRng, class Sh>
 __device__ __forceinline__ void visit(const DecreaseArgs &a, const SlotView &sv, Sh &sh, int w,
-                                      int src, uint32_t tag, uint32_t inc,
-                                      const int32_t *row_ptr)
+                                      int src, uint32_t tag, uint32_t inc, int2 r)
 {
-    int2 r = make_int2(0, 0);
-    if (kRng) r = make_int2(row_ptr[w], row_ptr[w + 1]);
     const unsigned long long tag64 = (unsigned long long)tag << 32;
     const unsigned long long old = __hip_atomic_fetch_max(&sv.map[w], tag64, __ATOMIC_RELAXED,
                                                           __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -165,6 +162,8 @@ __device__ __forceinline__ void locate(const Sh &sh, int cnt, int q, int &l, int
     quad = (sh.e0[lo] >> 2) + (q - sh.qpre[lo]);
 }
 
+// The live edges (mask) of one quad whose targets are in col. kRng: each target's row range
+// is read from row_ptr beside its claim.
 template <bool kRng, class Sh>
 __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView &sv, Sh &sh,
                                            uint32_t mask, uint4 col, int src, uint32_t tag,
@@ -176,7 +175,27 @@ __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView
         const int i = __builtin_ctz(mask);
         mask &= mask - 1;
         const uint32_t c = i == 0 ? col.x : i == 1 ? col.y : i == 2 ? col.z : col.w;
-        visit<kRng>(a, sv, sh, (int)c, src, tag, inc, row_ptr);
+        int2 r = make_int2(0, 0);
+        if (kRng) r = make_int2(row_ptr[c], row_ptr[c + 1]);
+        visit<kRng>(a, sv, sh, (int)c, src, tag, inc, r);
+    }
+}
+
+// The live edges (mask) of quad `quad` from their edge records (target, row start, row end):
+// h holds the record of the lowest live edge; the next one is loaded while this one is
+// claimed.
+template <class Sh>
+__device__ __forceinline__ void visit_edges(const DecreaseArgs &a, const SlotView &sv, Sh &sh,
+                                            uint32_t mask, uint4 h, int quad, int src,
+                                            uint32_t tag, uint32_t inc, uint32_t &live,
+                                            const uint4 *edge)
+{
+    live += (uint32_t)__builtin_popcount(mask);
+    while (mask) {
+        mask &= mask - 1;
+        const uint4 cur = h;
+        if (mask) h = edge[((size_t)quad << 2) + __builtin_ctz(mask)];
+        visit<true>(a, sv, sh, (int)cur.x, src, tag, inc, make_int2((int)cur.y, (int)cur.z));
     }
 }
 
@@ -185,13 +204,17 @@ __device__ __forceinline__ void visit_mask(const DecreaseArgs &a, const SlotView
 // thread);
 // the edge quads of a chunk are spread evenly over the workgroup, two independent quads in
 // flight per thread. A quad's thresholds are always read; its targets only when one of its
-// coins comes up live.
-template <int B, bool kLT, bool kRng>
+// coins comes up live (single calls under IC: only the live edges' records).
+// kMulti: many-instance launch. Row ranges of local vertices are kept (kRng) except in
+// linear-threshold single calls, which read row_ptr per frontier vertex.
+template <int B, bool kLT, bool kMulti>
 __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv, Shared<B> &sh,
                        bool from_seeds, int lo, int hi, uint32_t j, uint32_t tag,
                        uint32_t inc, uint32_t &scanned, uint32_t &live)
 {
     constexpr int kChunk = Shared<B>::kChunk;
+    constexpr bool kRng = kMulti || !kLT;
+    constexpr bool kEdge = !kMulti && !kLT;  // targets and row ranges from edge records
     const int tid = threadIdx.x;
     for (int base = lo; base < hi; base += kChunk) {
         const int first = tid * kPerThread;
@@ -248,7 +271,7 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
                 m2 = has2 ? live_mask_lt(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], b2,
                                          t2, c2)
                           : 0u;
-            } else if (B == kMultiBlock) {
+            } else if (kMulti) {
                 // many-instance launches: targets loaded beside the thresholds
                 c1 = c.col4[quad1];
                 c2 = c.col4[quad2];
@@ -257,6 +280,17 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
             } else {
                 m1 = live_mask(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], t1);
                 m2 = has2 ? live_mask(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], t2) : 0u;
+                if (kEdge) {
+                    // the records of the lowest live edge of each quad, both in flight
+                    uint4 h1 = make_uint4(0, 0, 0, 0), h2 = make_uint4(0, 0, 0, 0);
+                    if (m1) h1 = a.edge[((size_t)quad1 << 2) + __builtin_ctz(m1)];
+                    if (m2) h2 = a.edge[((size_t)quad2 << 2) + __builtin_ctz(m2)];
+                    visit_edges(a, sv, sh, m1, h1, quad1, from_seeds ? 0 : base + l1, tag, inc,
+                                live, a.edge);
+                    visit_edges(a, sv, sh, m2, h2, quad2, from_seeds ? 0 : base + l2, tag, inc,
+                                live, a.edge);
+                    continue;
+                }
                 if (m1) c1 = c.col4[quad1];
                 if (m2) c2 = c.col4[quad2];
             }
@@ -300,7 +334,7 @@ void decrease_kernel(DecreaseArgs a)
     sv.loc = a.ws.loc + slot * (size_t)a.ws.lcap;
     sv.lvl = a.ws.lvl + slot * (size_t)(a.ws.lcap + 1);
     sv.extra = a.ws.extra + slot * (size_t)a.ws.xcap;
-    sv.rng = kMulti ? a.ws.rng + slot * (size_t)a.ws.lcap : nullptr;
+    sv.rng = (kMulti || !kLT) ? a.ws.rng + slot * (size_t)a.ws.lcap : nullptr;
     uint32_t epoch = a.ws.epoch[slot];
     const uint32_t emax = 0xFFFFFFFFu >> a.ws.lbits;  // largest epoch the map entries hold
     const uint32_t count = a.sample_list ? *a.sample_count : a.theta;

@@ -22,6 +22,8 @@ struct imin_graph {
     std::vector<int32_t> col;
     int32_t *d_row_ptr = nullptr;
     uint4 *d_col4 = nullptr;      // edge targets, 4 per quad, padded to a whole quad
+    uint4 *d_edge = nullptr;      // independent cascade: one record per edge slot of d_col4,
+                                  // (target, target's row start, row end, 0)
     uint4 *d_thr4 = nullptr;      // working live thresholds, same layout: 0 on every edge into
                                   // a vertex of `masked`
     uint4 *d_thr_orig = nullptr;  // the thresholds ceil(p * 2^24) as created

@@ -57,8 +57,9 @@ struct Workspace {
     LocalVtx *loc = nullptr;   // slots * lcap
     int32_t *lvl = nullptr;    // slots * (lcap + 1): first local id of each BFS level
     int2 *extra = nullptr;     // slots * xcap: (source local id, target vertex -> local id)
-    int2 *rng = nullptr;       // slots * lcap, many-instance workspaces only: the row range
-                               // (row_ptr pair) of each local vertex, read when it is claimed
+    int2 *rng = nullptr;       // slots * lcap, except for linear-threshold single calls: the
+                               // row range (row_ptr pair) of each local vertex, known when it
+                               // is claimed
     uint32_t *epoch = nullptr; // slots: epoch of the slot's last sample
     uint32_t *dirty = nullptr; // slots: 1 when the slot's last counting launch left reach
                                // counts in its map (launch_flush_counts reads only those)
@@ -71,6 +72,9 @@ struct InstanceDesc;
 struct DecreaseArgs {
     const int32_t *row_ptr;  // n + 1
     const uint4 *col4;       // ceil(m / 4) quads of edge targets (4 edges = 16 bytes)
+    const uint4 *edge;       // single calls under IC: 4 * ceil(m / 4) records (target,
+                             // target's row start, row end, 0), so that a live edge's one
+                             // line also gives the row the next level expands
     const uint4 *thr4;       // ceil(m / 4) quads of live thresholds ceil(p * 2^24), 0 for
                              // edges into seeds and blocked vertices
     const uint4 *lo4;        // linear-threshold model: interval lower bounds (thr4 = upper)

@@ -98,7 +98,8 @@ struct Carve {
 };
 
 // Slot-major workgroup-kernel scratch of `slots` slots in the carve.
-bool carve_ws(Carve &c, imin::Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap)
+bool carve_ws(Carve &c, imin::Workspace &ws, int64_t n, int32_t slots, int64_t lcap, int64_t xcap,
+              bool rng)
 {
     int32_t lbits = 1;
     while (lbits < 32 && (int64_t(1) << lbits) <= lcap) ++lbits;
@@ -110,7 +111,7 @@ bool carve_ws(Carve &c, imin::Workspace &ws, int64_t n, int32_t slots, int64_t l
     ws.extra = c.take<int2>(S * (size_t)std::max<int64_t>(xcap, 1));
     ws.epoch = c.take<uint32_t>(S);
     ws.dirty = c.take<uint32_t>(S);
-    ws.rng = nullptr;
+    ws.rng = rng ? c.take<int2>(S * (size_t)lcap) : nullptr;
     ws.slots = slots;
     ws.n = n;
     ws.lcap = lcap;
@@ -151,20 +152,22 @@ int imin_decrease_noalloc(imin_graph *g, const int32_t *S, int32_t nS, const uin
     uint8_t *marks = blocked ? c.take<uint8_t>((size_t)n) : nullptr;
     uint32_t *sj = c.take<uint32_t>(theta);
     uint32_t *ovf = c.take<uint32_t>(theta);
+    // independent cascade: slots keep each claimed vertex's row range
+    const bool rng = g->model == IMIN_IC;
     imin::Workspace big_ws;
-    if (xcap < xmax && !carve_ws(c, big_ws, n, 2, lcap, xmax)) return IMIN_ERANGE;
+    if (xcap < xmax && !carve_ws(c, big_ws, n, 2, lcap, xmax, rng)) return IMIN_ERANGE;
     if (!c.fits) return IMIN_ERANGE;
     const size_t fixed = c.used;
     // as many workgroup slots as the rest holds, up to the usual count
     Carve probe{base, fixed};
     imin::Workspace one;
-    if (!carve_ws(probe, one, n, 1, lcap, xcap)) return IMIN_ERANGE;
-    const size_t per_slot = probe.used - fixed + 6 * 256;
+    if (!carve_ws(probe, one, n, 1, lcap, xcap, rng)) return IMIN_ERANGE;
+    const size_t per_slot = probe.used - fixed + 7 * 256;
     const int32_t slots = (int32_t)std::max<size_t>(
         1, std::min<size_t>((size_t)imin::kSlotsPerCu * g->num_cus,
                             (kScratchBytes - fixed) / per_slot));
     imin::Workspace main_ws;
-    if (!carve_ws(c, main_ws, n, slots, lcap, xcap)) return IMIN_ERANGE;
+    if (!carve_ws(c, main_ws, n, slots, lcap, xcap, rng)) return IMIN_ERANGE;
     if (xcap >= xmax) big_ws = imin::Workspace();
 
     hipStream_t st = g->stream;
