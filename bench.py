@@ -239,8 +239,8 @@ def bench_batched(args, with_cpu: bool) -> dict:
         "reached_per_sample": stats["reached"] / max(1, stats["samples"]),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "decrease_pack_kernel with the wave and workgroup kernels of "
-                               "its hand-overs (one round's sampling launches)",
+                     "kernel": "decrease_pack_kernel with the workgroup kernel for its "
+                               "hand-overs (one round's sampling launches)",
                      "algorithmic_bytes_per_launch": alg / rounds,
                      "avg_launch_ms": kernel_ms / rounds},
     }

@@ -525,7 +525,7 @@ int multi_round(MultiScratch &ms, const imin::InstanceDesc *inst, int32_t ninst,
     // packed kernel keeps the seed level's edge coins in registers); what outgrows it goes
     // straight to the workgroup kernel through a device-side list. The hand-overs are the
     // few larger samples (over 63 vertices or 64 extra edges), which the workgroup kernel's
-    // 1024 slots finish sooner than one wavefront each would. Without the packed kernel
+    // 2048 slots finish sooner than one wavefront each would. Without the packed kernel
     // (linear threshold, or switched off) the one-sample-per-wave kernel takes every sample
     // first and hands its overflow on.
     const bool pack = !lt && shape.pack_per_cu >= 0;

@@ -11,7 +11,7 @@ namespace imin {
 // calls, the server), whose handed-over samples are mostly of moderate size and gain more
 // from having more of them in flight.
 constexpr int kBlock = 1024;
-constexpr int kMultiBlock = 512;
+constexpr int kMultiBlock = 256;
 // Workgroup slots per compute unit: as many as its 32 wave slots hold.
 constexpr int kSlotsPerCu = 2048 / kBlock;
 constexpr int kMultiSlotsPerCu = 2048 / kMultiBlock;
