@@ -242,6 +242,7 @@ void describe(imin_graph *g, int32_t nseeds, uint64_t seed, uint32_t theta)
     imin::InstanceDesc &I = g->h_inst;
     I.row_ptr = g->d_row_ptr;
     I.col4 = g->d_col4;
+    I.edge = g->d_edge;
     I.thr4 = g->d_thr4;
     I.lo4 = g->d_lo4;
     I.in_ptr = g->d_in_ptr;

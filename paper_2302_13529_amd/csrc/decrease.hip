@@ -68,6 +68,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *tot
 struct Call {
     const int32_t *row_ptr;
     const uint4 *col4;
+    const uint4 *edge;
     const uint4 *thr4;
     const uint4 *lo4;
     const int32_t *seeds;
@@ -203,10 +204,12 @@ __device__ __forceinline__ void visit_edges(const DecreaseArgs &a, const SlotVie
 // The frontier goes in chunks of B * kPerThread entries (kPerThread consecutive entries per
 // thread);
 // the edge quads of a chunk are spread evenly over the workgroup, two independent quads in
-// flight per thread. A quad's thresholds are always read; its targets only when one of its
-// coins comes up live (single calls under IC: only the live edges' records).
-// kMulti: many-instance launch. Row ranges of local vertices are kept (kRng) except in
-// linear-threshold single calls, which read row_ptr per frontier vertex.
+// flight per thread. A quad's thresholds are always read. Under IC only its live edges'
+// records (target and row range) are read; under LT its targets are read first, since the
+// coins depend on them, and a claimed target's row range comes from row_ptr in
+// many-instance launches. kMulti: many-instance launch. Row ranges of local vertices are
+// kept (kRng) except in linear-threshold single calls, which read row_ptr per frontier
+// vertex.
 template <int B, bool kLT, bool kMulti>
 __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv, Shared<B> &sh,
                        bool from_seeds, int lo, int hi, uint32_t j, uint32_t tag,
@@ -214,7 +217,6 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
 {
     constexpr int kChunk = Shared<B>::kChunk;
     constexpr bool kRng = kMulti || !kLT;
-    constexpr bool kEdge = !kMulti && !kLT;  // targets and row ranges from edge records
     const int tid = threadIdx.x;
     for (int base = lo; base < hi; base += kChunk) {
         const int first = tid * kPerThread;
@@ -259,45 +261,34 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
             locate(sh, cnt, has2 ? q2 : q, l2, quad2);
             const uint4 t1 = c.thr4[quad1];
             const uint4 t2 = c.thr4[quad2];
-            uint32_t m1, m2;
-            uint4 c1 = make_uint4(0, 0, 0, 0), c2 = make_uint4(0, 0, 0, 0);
             if (kLT) {
                 // a vertex-keyed choice per edge: the targets are needed first
                 const uint4 b1 = c.lo4[quad1];
                 const uint4 b2 = c.lo4[quad2];
-                c1 = c.col4[quad1];
-                c2 = c.col4[quad2];
-                m1 = live_mask_lt(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], b1, t1, c1);
-                m2 = has2 ? live_mask_lt(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], b2,
-                                         t2, c2)
-                          : 0u;
-            } else if (kMulti) {
-                // many-instance launches: targets loaded beside the thresholds
-                c1 = c.col4[quad1];
-                c2 = c.col4[quad2];
-                m1 = live_mask(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], t1);
-                m2 = has2 ? live_mask(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], t2) : 0u;
+                const uint4 c1 = c.col4[quad1];
+                const uint4 c2 = c.col4[quad2];
+                const uint32_t m1 =
+                    live_mask_lt(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], b1, t1, c1);
+                const uint32_t m2 = has2 ? live_mask_lt(quad2, j, c.key_lo, c.key_hi, sh.e0[l2],
+                                                        sh.e1[l2], b2, t2, c2)
+                                         : 0u;
+                visit_mask<kRng>(a, sv, sh, m1, c1, from_seeds ? 0 : base + l1, tag, inc, live,
+                                 c.row_ptr);
+                visit_mask<kRng>(a, sv, sh, m2, c2, from_seeds ? 0 : base + l2, tag, inc, live,
+                                 c.row_ptr);
             } else {
-                m1 = live_mask(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], t1);
-                m2 = has2 ? live_mask(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], t2) : 0u;
-                if (kEdge) {
-                    // the records of the lowest live edge of each quad, both in flight
-                    uint4 h1 = make_uint4(0, 0, 0, 0), h2 = make_uint4(0, 0, 0, 0);
-                    if (m1) h1 = a.edge[((size_t)quad1 << 2) + __builtin_ctz(m1)];
-                    if (m2) h2 = a.edge[((size_t)quad2 << 2) + __builtin_ctz(m2)];
-                    visit_edges(a, sv, sh, m1, h1, quad1, from_seeds ? 0 : base + l1, tag, inc,
-                                live, a.edge);
-                    visit_edges(a, sv, sh, m2, h2, quad2, from_seeds ? 0 : base + l2, tag, inc,
-                                live, a.edge);
-                    continue;
-                }
-                if (m1) c1 = c.col4[quad1];
-                if (m2) c2 = c.col4[quad2];
+                const uint32_t m1 = live_mask(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], t1);
+                const uint32_t m2 =
+                    has2 ? live_mask(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], t2) : 0u;
+                // the records of the lowest live edge of each quad, both in flight
+                uint4 h1 = make_uint4(0, 0, 0, 0), h2 = make_uint4(0, 0, 0, 0);
+                if (m1) h1 = c.edge[((size_t)quad1 << 2) + __builtin_ctz(m1)];
+                if (m2) h2 = c.edge[((size_t)quad2 << 2) + __builtin_ctz(m2)];
+                visit_edges(a, sv, sh, m1, h1, quad1, from_seeds ? 0 : base + l1, tag, inc, live,
+                            c.edge);
+                visit_edges(a, sv, sh, m2, h2, quad2, from_seeds ? 0 : base + l2, tag, inc, live,
+                            c.edge);
             }
-            visit_mask<kRng>(a, sv, sh, m1, c1, from_seeds ? 0 : base + l1, tag, inc, live,
-                             c.row_ptr);
-            visit_mask<kRng>(a, sv, sh, m2, c2, from_seeds ? 0 : base + l2, tag, inc, live,
-                             c.row_ptr);
         }
         __syncthreads();
     }
@@ -354,15 +345,15 @@ void decrease_kernel(DecreaseArgs a)
         const uint32_t j = a.sample_list ? a.sample_list[idx] : idx;
         // This sample's problem: the launch's own, or an instance of a many-instance launch
         // (all instances' vertex ids fit the slot maps).
-        Call c{a.row_ptr, a.col4, a.thr4, a.lo4, a.seeds, a.nseeds, a.key_lo, a.key_hi, a.D,
-               a.stats};
+        Call c{a.row_ptr, a.col4, a.edge, a.thr4,   a.lo4, a.seeds,
+               a.nseeds,  a.key_lo, a.key_hi, a.D, a.stats};
         uint32_t inst_i = 0;
         if (kMulti) {
             inst_i = __builtin_amdgcn_readfirstlane(a.sample_inst[idx]);
             const InstanceDesc &I = a.inst[inst_i];
             const unsigned long long key =
                 (((unsigned long long)I.seed_hi << 32) | I.seed_lo) + a.round;
-            c = Call{I.row_ptr, I.col4,  I.thr4,        I.lo4, I.seeds, I.nseeds,
+            c = Call{I.row_ptr, I.col4,  I.edge,        I.thr4, I.lo4, I.seeds, I.nseeds,
                      (uint32_t)key, (uint32_t)(key >> 32), I.D,     I.stats};
         }
         if (epoch >= emax) {

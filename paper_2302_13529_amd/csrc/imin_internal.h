@@ -126,6 +126,8 @@ constexpr int kSmallWaves = 4;
 struct InstanceDesc {
     const int32_t *row_ptr;
     const uint4 *col4;
+    const uint4 *edge;        // independent cascade: per-edge records (target, target's row
+                              // start, row end, 0), as DecreaseArgs::edge
     uint4 *thr4;              // working thresholds (the batched argmax masks its winners)
     const uint4 *lo4;         // linear-threshold model: interval lower bounds
     const int32_t *in_ptr;    // in-edges of v: in_edge[in_ptr[v] .. in_ptr[v+1])

@@ -180,6 +180,7 @@ void carve(imin_server *s, Query &q)
     I.x = reinterpret_cast<int32_t *>(p);
     I.row_ptr = g->d_row_ptr;
     I.col4 = g->d_col4;
+    I.edge = g->d_edge;
     I.lo4 = g->d_lo4;
     I.in_ptr = g->d_in_ptr;
     I.in_edge = g->d_in_edge;
