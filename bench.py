@@ -437,7 +437,7 @@ def main() -> int:
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(samples would shard across GPUs with one integer reduction of the counts "
-              "per round; see the design notes)", file=sys.stderr)
+              "per round)", file=sys.stderr)
         return 2
     if args.workload == "batched":
         b = bench_batched(args, with_cpu=not args.no_cpu)
