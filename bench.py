@@ -435,7 +435,7 @@ def main() -> int:
                     help="batched workload: tune the launch shape if no cached entry exists")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(samples would shard across GPUs with one integer reduction of the counts "
               "per round)", file=sys.stderr)
         return 2
