@@ -65,7 +65,11 @@ enum {
     IMIN_GR = 1  /* GreedyReplace, Algorithm 4 */
 };
 
-/* Opaque handle: the device-resident graph and its per-slot scratch. */
+/* Opaque handle: the device-resident graph and its per-slot scratch. The calls take it
+ * non-const: they write device state it owns (the working thresholds that mask seeds and
+ * blockers, the counters, the slots' maps), which is also why calls on one handle must not
+ * overlap. The graph itself is never changed: every call leaves the thresholds as created
+ * for the next one. */
 typedef struct imin_graph imin_graph;
 
 /* Work counters of a call (summed over every Algorithm 2 call it made). */
@@ -121,7 +125,10 @@ IMIN_API int imin_graph_create_model(int32_t n, int32_t m, const int32_t *row_pt
                                      const int32_t *col, const float *prob, int model,
                                      imin_graph **out);
 
-/* Release a handle and all device memory it owns. NULL is ignored. */
+/* Release a handle and all device memory it owns (the graph of imin_graph_create, its
+ * workgroup scratch, and the scratch of the batches and servers it leads). No passage of the
+ * paper defines this: it is the resource side of the graph residency the calls below rely
+ * on. NULL is ignored. */
 IMIN_API void imin_graph_destroy(imin_graph *g);
 
 /*
@@ -368,7 +375,8 @@ IMIN_API int imin_decrease_noalloc(imin_graph *g, const int32_t *S, int32_t nS,
                                    const uint8_t *blocked, uint32_t theta, uint64_t seed,
                                    uint64_t *d_counts, imin_stats *stats);
 
-/* Human-readable text of a status code (static storage). */
+/* Human-readable text of a status code (static storage). An interface convenience; no
+ * passage of the paper defines it. */
 IMIN_API const char *imin_strerror(int status);
 
 #ifdef __cplusplus
