@@ -68,8 +68,9 @@ enum {
 /* Opaque handle: the device-resident graph and its per-slot scratch. The calls take it
  * non-const: they write device state it owns (the working thresholds that mask seeds and
  * blockers, the counters, the slots' maps), which is also why calls on one handle must not
- * overlap. The graph itself is never changed: every call leaves the thresholds as created
- * for the next one. */
+ * overlap. The graph itself never changes: each call works from the thresholds as created,
+ * restoring whatever an earlier call left masked before it masks its own seeds and
+ * blockers. */
 typedef struct imin_graph imin_graph;
 
 /* Work counters of a call (summed over every Algorithm 2 call it made). */
