@@ -214,7 +214,7 @@ typedef struct {
     int32_t graph;
     int32_t pack_per_cu;  /* batched calls and the server: workgroups per compute unit of the
                              kernel that runs several small samples per wavefront (0: the
-                             default, 2; -1: that kernel off, every sample starts in the
+                             default, 4; -1: that kernel off, every sample starts in the
                              one-sample-per-wave kernel). With it on, its hand-overs go to
                              the workgroup kernel and the other fields have no effect */
 } imin_launch;

@@ -24,9 +24,9 @@ constexpr int32_t kDefaultQuadLimit = 2048;
 constexpr int32_t kDefaultPickDiv = 4;
 // Packed kernel: a frontier vertex with more edge quads than this hands its sample over.
 constexpr int32_t kDefaultPackQuadLimit = 256;
-// Packed kernel workgroups per compute unit: as many as its LDS allows (kPackWaves waves of
-// kPackG samples each per workgroup).
-constexpr int kPackGroupsPerCu = 2;
+// Packed kernel workgroups per compute unit (kPackWaves waves of kPackG samples each): its
+// registers allow 4 waves per SIMD, that is 4 workgroups.
+constexpr int kPackGroupsPerCu = 4;
 
 int pack_grid(int num_cus, const imin_launch &l)
 {
