@@ -151,26 +151,32 @@ def cpu_baseline(inst, theta_sample: int, model: str = "ic") -> dict:
                       f"(every {cores}-th sample each), {dt:.1f} s"}
 
 
-def bench_batched(args, with_cpu: bool) -> dict:
+def batched_cpu_baseline(insts) -> dict:
+    """The checker on round 0 (full theta) of every batched instance, in forked processes;
+    call it before this process touches the GPU."""
+    print("[bench] cpu baseline (batched instances)", file=sys.stderr, flush=True)
+    cores = cpu_workers()
+    _CPU_JOB.update(insts=insts)
+    res, cdt = _parallel(_cpu_instances, [list(range(w, len(insts), cores))
+                                          for w in range(cores)])
+    return {"value": sum(res) / cdt, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"round 0 (full theta) of all {len(insts)} instances, C checker in "
+                      f"{cores} processes (every {cores}-th instance each), {cdt:.1f} s"}
+
+
+def bench_batched(args, with_cpu: bool, insts=None, cpu=None) -> dict:
     """256 Chung-Lu instances: every instance as a plain imin_greedy call, then args.steps
     batched calls over all of them; blockers compared with each other and with the checker's
-    stored results."""
+    stored results. `insts` and `cpu` may come from an earlier generation and checker run."""
     import torch
     from paper_2302_13529_amd import binding, graphgen as gg
 
-    print("[bench] generating 256 batched instances", file=sys.stderr, flush=True)
-    insts = gg.batched_instances()
-    cpu = None
-    if with_cpu:
+    if insts is None:
+        print("[bench] generating 256 batched instances", file=sys.stderr, flush=True)
+        insts = gg.batched_instances()
+    if with_cpu and cpu is None:
         # the checker's processes fork before this process touches the GPU
-        print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        cores = cpu_workers()
-        _CPU_JOB.update(insts=insts)
-        res, cdt = _parallel(_cpu_instances, [list(range(w, len(insts), cores))
-                                              for w in range(cores)])
-        cpu = {"value": sum(res) / cdt, "unit": "samples/s", "cores": cores, "kind": "oracle",
-               "sample": f"round 0 (full theta) of all {len(insts)} instances, C checker in "
-                         f"{cores} processes (every {cores}-th instance each), {cdt:.1f} s"}
+        cpu = batched_cpu_baseline(insts)
     graphs = [binding.Graph(t.row_ptr, t.col, t.prob) for t in insts]
     probs = [(g.handle, t.seeds, t.b, t.theta, t.seed) for g, t in zip(graphs, insts)]
     from paper_2302_13529_amd import autotune
@@ -453,9 +459,16 @@ def main() -> int:
         out.update(sv)
         print(json.dumps(out), flush=True)
         return 0
+    insts = cpu_b = None
+    if args.workload == "all":
+        # the batched instances' checker run forks before anything touches the GPU
+        from paper_2302_13529_amd import graphgen as gg
+        insts = gg.batched_instances()
+        if not args.no_cpu:
+            cpu_b = batched_cpu_baseline(insts)
     out = bench_headline(args)
     if args.workload == "all":
-        out["batched"] = bench_batched(args, with_cpu=False)
+        out["batched"] = bench_batched(args, with_cpu=False, insts=insts, cpu=cpu_b)
         out["served"] = bench_served(args)
     print(json.dumps(out), flush=True)
     return 0
