@@ -245,6 +245,7 @@ void describe(imin_graph *g, int32_t nseeds, uint64_t seed, uint32_t theta)
     I.edge = g->d_edge;
     I.thr4 = g->d_thr4;
     I.lo4 = g->d_lo4;
+    I.tl = g->d_tl;
     I.in_ptr = g->d_in_ptr;
     I.in_edge = g->d_in_edge;
     I.inelig = g->d_inelig;
@@ -363,6 +364,7 @@ int launch_large_on(imin_graph *g, const LargeTarget &t, uint32_t theta, uint64_
     a.edge = g->d_edge;
     a.thr4 = t.thr4;
     a.lo4 = g->d_lo4;
+    a.tl = g->d_tl;
     a.lt = g->model == IMIN_LT ? 1 : 0;
     a.seeds = t.seeds;
     a.nseeds = t.nseeds;
@@ -766,6 +768,7 @@ void destroy(imin_graph *g)
     dfree(g->d_thr4);
     dfree(g->d_thr_orig);
     dfree(g->d_lo4);
+    dfree(g->d_tl);
     dfree(g->d_in_ptr);
     dfree(g->d_in_edge);
     dfree(g->d_inelig);
@@ -1003,6 +1006,7 @@ int imin_graph_create_model(int32_t n, int32_t m, const int32_t *row_ptr, const 
         ok(hipMalloc(&g->d_part_i, (size_t)g->parts * sizeof(int32_t))) &&
         ok(hipMalloc(&g->d_x, sizeof(int32_t))) &&
         (model != IMIN_LT || ok(hipMalloc(&g->d_lo4, hlo.size() * sizeof(uint32_t)))) &&
+        (model != IMIN_LT || ok(hipMalloc(&g->d_tl, 2 * hlo.size() * sizeof(uint32_t)))) &&
         (model != IMIN_IC || ok(hipMalloc(&g->d_edge, hcol.size() * sizeof(uint4))));
     if (!good) {
         (void)hipGetLastError();
@@ -1025,6 +1029,26 @@ int imin_graph_create_model(int32_t n, int32_t m, const int32_t *row_ptr, const 
                                            hipMemcpyHostToDevice)))) {
         destroy(g);
         return IMIN_EDEVICE;
+    }
+    if (model == IMIN_LT) {
+        // per quad: its 4 targets, then its 4 lower bounds
+        std::vector<uint32_t> htl;
+        try {
+            htl.assign(2 * hlo.size(), 0u);
+        } catch (...) {
+            destroy(g);
+            return IMIN_ENOMEM;
+        }
+        for (size_t q = 0; q < hlo.size() / 4; ++q)
+            for (int k = 0; k < 4; ++k) {
+                htl[8 * q + k] = hcol[4 * q + k];
+                htl[8 * q + 4 + k] = hlo[4 * q + k];
+            }
+        if (!ok(hipMemcpy(g->d_tl, htl.data(), htl.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice))) {
+            destroy(g);
+            return IMIN_EDEVICE;
+        }
     }
     if (model == IMIN_IC) {
         // edge records: padding slots past m stay zero (their coins are never live)

@@ -71,6 +71,7 @@ struct Call {
     const uint4 *edge;
     const uint4 *thr4;
     const uint4 *lo4;
+    const uint4 *tl;
     const int32_t *seeds;
     int32_t nseeds;
     uint32_t key_lo, key_hi;
@@ -262,11 +263,12 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
             const uint4 t1 = c.thr4[quad1];
             const uint4 t2 = c.thr4[quad2];
             if (kLT) {
-                // a vertex-keyed choice per edge: the targets are needed first
-                const uint4 b1 = c.lo4[quad1];
-                const uint4 b2 = c.lo4[quad2];
-                const uint4 c1 = c.col4[quad1];
-                const uint4 c2 = c.col4[quad2];
+                // a vertex-keyed choice per edge: the targets are needed first; they share
+                // a 32-byte block with the quad's lower bounds
+                const uint4 c1 = c.tl[2 * (size_t)quad1];
+                const uint4 b1 = c.tl[2 * (size_t)quad1 + 1];
+                const uint4 c2 = c.tl[2 * (size_t)quad2];
+                const uint4 b2 = c.tl[2 * (size_t)quad2 + 1];
                 const uint32_t m1 =
                     live_mask_lt(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], b1, t1, c1);
                 const uint32_t m2 = has2 ? live_mask_lt(quad2, j, c.key_lo, c.key_hi, sh.e0[l2],
@@ -345,16 +347,16 @@ void decrease_kernel(DecreaseArgs a)
         const uint32_t j = a.sample_list ? a.sample_list[idx] : idx;
         // This sample's problem: the launch's own, or an instance of a many-instance launch
         // (all instances' vertex ids fit the slot maps).
-        Call c{a.row_ptr, a.col4, a.edge, a.thr4,   a.lo4, a.seeds,
-               a.nseeds,  a.key_lo, a.key_hi, a.D, a.stats};
+        Call c{a.row_ptr, a.col4,   a.edge,   a.thr4, a.lo4,  a.tl,
+               a.seeds,   a.nseeds, a.key_lo, a.key_hi, a.D, a.stats};
         uint32_t inst_i = 0;
         if (kMulti) {
             inst_i = __builtin_amdgcn_readfirstlane(a.sample_inst[idx]);
             const InstanceDesc &I = a.inst[inst_i];
             const unsigned long long key =
                 (((unsigned long long)I.seed_hi << 32) | I.seed_lo) + a.round;
-            c = Call{I.row_ptr, I.col4,  I.edge,        I.thr4, I.lo4, I.seeds, I.nseeds,
-                     (uint32_t)key, (uint32_t)(key >> 32), I.D,     I.stats};
+            c = Call{I.row_ptr, I.col4,  I.edge,        I.thr4, I.lo4, I.tl, I.seeds,
+                     I.nseeds, (uint32_t)key, (uint32_t)(key >> 32), I.D, I.stats};
         }
         if (epoch >= emax) {
             // every epoch value is used up: clear this slot's map (the barrier below orders

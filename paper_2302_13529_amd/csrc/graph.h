@@ -29,6 +29,8 @@ struct imin_graph {
     uint4 *d_thr_orig = nullptr;  // the thresholds ceil(p * 2^24) as created
     int model = 0;                // IMIN_IC or IMIN_LT
     uint4 *d_lo4 = nullptr;       // linear-threshold model: interval lower bounds
+    uint4 *d_tl = nullptr;        // linear-threshold model: per quad, its targets and then its
+                                  // lower bounds (32 bytes, one line)
     int32_t *d_in_ptr = nullptr;  // in-edges of v: d_in_edge[d_in_ptr[v] .. d_in_ptr[v+1])
     int32_t *d_in_edge = nullptr; // edge ids, grouped by target
     hipStream_t stream = nullptr;

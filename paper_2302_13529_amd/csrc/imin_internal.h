@@ -78,6 +78,8 @@ struct DecreaseArgs {
     const uint4 *thr4;       // ceil(m / 4) quads of live thresholds ceil(p * 2^24), 0 for
                              // edges into seeds and blocked vertices
     const uint4 *lo4;        // linear-threshold model: interval lower bounds (thr4 = upper)
+    const uint4 *tl;         // linear-threshold model: 2 * ceil(m / 4) quads, quad q's targets
+                             // at 2q and its lower bounds at 2q + 1
     int32_t lt;              // 1: linear-threshold model, 0: independent cascade
     const int32_t *seeds;    // distinct seeds
     int32_t nseeds;
@@ -130,6 +132,8 @@ struct InstanceDesc {
                               // start, row end, 0), as DecreaseArgs::edge
     uint4 *thr4;              // working thresholds (the batched argmax masks its winners)
     const uint4 *lo4;         // linear-threshold model: interval lower bounds
+    const uint4 *tl;          // linear-threshold model: targets and lower bounds, as
+                              // DecreaseArgs::tl
     const int32_t *in_ptr;    // in-edges of v: in_edge[in_ptr[v] .. in_ptr[v+1])
     const int32_t *in_edge;   // edge ids
     uint32_t *inelig;         // bit v set: v is a seed or blocked (the argmax adds winners)

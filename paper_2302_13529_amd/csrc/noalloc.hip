@@ -230,8 +230,10 @@ int imin_decrease_noalloc(imin_graph *g, const int32_t *S, int32_t nS, const uin
     imin::InstanceDesc I{};
     I.row_ptr = g->d_row_ptr;
     I.col4 = g->d_col4;
+    I.edge = g->d_edge;
     I.thr4 = g->d_thr4;
     I.lo4 = g->d_lo4;
+    I.tl = g->d_tl;
     I.in_ptr = g->d_in_ptr;
     I.in_edge = g->d_in_edge;
     I.inelig = bits;

@@ -182,6 +182,7 @@ void carve(imin_server *s, Query &q)
     I.col4 = g->d_col4;
     I.edge = g->d_edge;
     I.lo4 = g->d_lo4;
+    I.tl = g->d_tl;
     I.in_ptr = g->d_in_ptr;
     I.in_edge = g->d_in_edge;
     I.thr_orig = g->d_thr_orig;
