@@ -16,14 +16,14 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = 0u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * x0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, x0);
-        const uint32_t lo1 = 0xCD9E8D57u * x2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, x2);
-        x0 = hi1 ^ x1 ^ k0;
-        x1 = lo1;
-        x2 = hi0 ^ x3 ^ k1;
-        x3 = lo0;
+        // each 32 x 32 -> 64-bit product in one multiply (v_mad_u64_u32), not a low and a
+        // high multiply
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        x0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        x1 = (uint32_t)p1;
+        x2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        x3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
