@@ -1,9 +1,10 @@
-"""The wave-per-sample kernel and the batched greedy call against the CPU oracle.
+"""The wavefront-level kernels and the batched greedy call against the CPU oracle.
 
-Every sample first runs in one wavefront; the ones that outgrow it (more than 255 reached
-vertices, more than 256 non-tree live edges, or a heavy frontier chunk) are handed to the
-workgroup kernel. Counts and choices must not depend on which kernel finished a sample, so
-everything here is compared bit-exactly with the oracle and with the plain per-graph calls.
+A sample first runs in a wavefront: in single calls and LT batches one sample per wave, in
+IC batches several per wave (the packed kernel). The ones that outgrow it (too many reached
+vertices or non-tree live edges, or a heavy frontier vertex) are handed to the workgroup
+kernel. Counts and choices must not depend on which kernel finished a sample, so everything
+here is compared bit-exactly with the oracle and with the plain per-graph calls.
 """
 import numpy as np
 import pytest
@@ -127,7 +128,7 @@ def test_batch_equals_plain_and_oracle(gpu, batch16):
 
 
 def test_batch_with_handed_over_samples_and_existing_scratch(gpu, batch16):
-    """Instances whose samples outgrow the wave kernel, one of whose graphs already holds
+    """Instances whose samples outgrow the packed kernel, one of whose graphs already holds
     workgroup scratch and the masked thresholds of other seeds from an earlier plain call."""
     t0, t1 = batch16[0], batch16[1]
     prp, pc, pp = _path_graph()
@@ -150,8 +151,8 @@ def test_batch_with_handed_over_samples_and_existing_scratch(gpu, batch16):
         assert list(B) == list(Bo), i
         assert st["reached"] == so["reached"], i
     # round 0 of the path reaches 299 vertices in every sample (all handed over), so its
-    # later rounds skip the wave kernel and go straight to the workgroup kernel; the tiny
-    # graph's samples stay in the wave kernel
+    # later rounds skip the packed kernel and go straight to the workgroup kernel; the tiny
+    # graph's samples stay in the packed kernel
     assert res[0][1]["wave_samples"] == 0 and res[0][1]["samples"] == 4 * 60
     assert res[2][1]["wave_samples"] > 0
     # the handles keep working for plain calls afterwards
