@@ -123,3 +123,26 @@ def test_lt_weights_validated(gpu):
     with pytest.raises(gpu.IminError):
         gpu.Graph(rp, c, w, model=7)
     gpu.Graph(rp, c, w).close()  # fine under IC
+
+
+def test_lt_spread_counts_equal_the_oracle(gpu):
+    """Reachability-only sampling (imin_spread) under the linear-threshold model: the reached
+    sum is an integer and must equal the checker's, on every kernel path, with and without
+    blockers, and equal the counters of the full decrease call."""
+    t = gg.tiny_plain()
+    g = gpu.Graph(t.row_ptr, t.col, t.prob, model=gpu.IMIN_LT)
+    rng = np.random.default_rng(4)
+    blocked = np.zeros(t.n, np.uint8)
+    blocked[[v for v in rng.choice(t.n, 40, replace=False) if v not in t.seeds]] = 1
+    for blk in (None, blocked):
+        for enable in (-1, 0, 1):
+            g.set_small(enable)
+            case(f"LT tiny spread, blocked={blk is not None}, wave kernel {enable}")
+            s, st = g.spread(t.seeds, blk, 2000, 23)
+            _, so = orc.decrease(t.n, t.row_ptr, t.col, t.prob, t.seeds, blk, 2000, 23,
+                                 model=orc.LT)
+            assert st["samples"] == 2000
+            for k in ("reached", "edges_scanned", "live_edges"):
+                assert st[k] == so[k], (k, st[k], so[k])
+            assert s == len(set(t.seeds.tolist())) + so["reached"] / 2000
+    g.close()
