@@ -2,8 +2,8 @@
 imin_decrease on the same graph and arguments: the counts into a caller-owned device buffer
 must equal the plain call's bit for bit, with identical work counters, on two calls in a
 row (the second on a smaller input, reusing the same static scratch), with blocked vertices
-and duplicate seeds, interleaved with plain calls that leave thresholds masked, and with the
-errors of a graph too large for the scratch."""
+and duplicate seeds, interleaved with plain calls that leave thresholds masked, under the
+linear-threshold model, and with the errors of a graph too large for the scratch."""
 import numpy as np
 import pytest
 
@@ -72,6 +72,20 @@ def test_noalloc_hand_over_and_spill_paths(gpu):
     g = gpu.Graph(rp, c, p)
     g.set_launch(0, 64)  # a small extra-edge capacity for the plain call as well
     _check(gpu, g, k, [0], None, 30, 5, "dense 120")
+    g.close()
+
+
+def test_noalloc_linear_threshold(gpu):
+    """A linear-threshold graph: its samples take the triggering model's kernel paths
+    (vertex-keyed choices, no kept row ranges), through the wave kernel and the workgroup
+    kernel, with blocked vertices."""
+    t = gg.tiny_plain()
+    g = gpu.Graph(t.row_ptr, t.col, t.prob, model=gpu.IMIN_LT)
+    _check(gpu, g, t.n, t.seeds, None, 600, 9, "LT tiny, theta 600")
+    blk = np.zeros(t.n, np.uint8)
+    blk[[3, 29, 511]] = 1
+    blk[t.seeds] = 0
+    _check(gpu, g, t.n, t.seeds, blk, 300, 4, "LT tiny, blocked, theta 300")
     g.close()
 
 
