@@ -351,7 +351,9 @@ int kernel_events(imin_graph *g, hipEvent_t *a, hipEvent_t *b)
 
 // The workgroup-per-sample kernel with Philox key `key` over samples 0..theta-1, or over
 // the device list `list` of *count samples (at most theta), then the large-scratch launch
-// for the samples that overflowed it. D and the stats accumulate.
+// for the samples that overflowed it. D and the stats accumulate: the main launch's slots
+// decide one by one whether to keep reach counts in their maps (count_reach allows it),
+// and the flush after the launches adds what they kept into D.
 int launch_large_on(imin_graph *g, const LargeTarget &t, uint32_t theta, uint64_t key,
                     const uint32_t *list, const uint32_t *count, bool reach_only)
 {
