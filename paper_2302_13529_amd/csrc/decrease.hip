@@ -279,7 +279,8 @@ __device__ void expand(const DecreaseArgs &a, const Call &c, const SlotView &sv,
                 visit_mask<kRng>(a, sv, sh, m2, c2, from_seeds ? 0 : base + l2, tag, inc, live,
                                  c.row_ptr);
             } else {
-                const uint32_t m1 = live_mask(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], t1);
+                const uint32_t m1 =
+                    live_mask(quad1, j, c.key_lo, c.key_hi, sh.e0[l1], sh.e1[l1], t1);
                 const uint32_t m2 =
                     has2 ? live_mask(quad2, j, c.key_lo, c.key_hi, sh.e0[l2], sh.e1[l2], t2) : 0u;
                 // the records of the lowest live edge of each quad, both in flight
@@ -301,6 +302,16 @@ __device__ __forceinline__ int nca(const LocalVtx *t, int x, int y)
     while (x != y) {
         if (x > y) x = t[x].tdom;
         else y = t[y].tdom;
+    }
+    return x;
+}
+
+// The same walk over tentative dominators held in LDS.
+__device__ __forceinline__ int nca_lds(const int *dom, int x, int y)
+{
+    while (x != y) {
+        if (x > y) x = dom[x];
+        else y = dom[y];
     }
     return x;
 }
@@ -436,85 +447,159 @@ void decrease_kernel(DecreaseArgs a)
         }
         __syncthreads();
 
-        // Dominator tree: Jacobi NCA steps over vertices with several reached predecessors.
-        // The subtree-size field of such a vertex holds the next tentative dominator
-        // meanwhile, and is reset to 1 afterwards.
-        if (nX > 0) {
-            // First one Gauss-Seidel sweep: the extra edges in list order (roughly the BFS
-            // order of their sources), B at a time, each chunk one step over its targets on
-            // the tree the earlier chunks left. A step over some vertices and some of their
-            // predecessors keeps every dominator of v on v's tree path (a dominator of v
-            // dominates each predecessor) and only moves t(v) up, so the Jacobi rounds below
-            // still end at the dominator tree; they just have less left to change.
-            for (int x0 = 0; x0 < nX; x0 += B) {
-                const int x = x0 + tid;
-                int2 e = make_int2(0, 0);
-                if (x < nX) {
-                    e = sv.extra[x];
-                    sv.loc[e.y].csz = sv.loc[e.y].tdom;
-                }
-                __syncthreads();
-                if (x < nX) {
-                    const int tv = sv.loc[e.y].tdom;
-                    const int m1 = nca(sv.loc, tv, e.x);
-                    const int m2 = nca(sv.loc, tv, sv.loc[e.y].par0);
-                    const int mm = min(m1, m2);
-                    if (mm < tv)
-                        __hip_atomic_fetch_min(&sv.loc[e.y].csz, mm, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-                __syncthreads();
-                if (x < nX) sv.loc[e.y].tdom = sv.loc[e.y].csz;
-                __syncthreads();
-            }
-            for (;;) {
-                for (int x = tid; x < nX; x += B) {
-                    const int v = sv.extra[x].y;
-                    sv.loc[v].csz = sv.loc[v].tdom;
-                }
-                if (tid == 0) sh.changed = 0;
-                __syncthreads();
-                for (int x = tid; x < nX; x += B) {
-                    const int2 e = sv.extra[x];
-                    const int tv = sv.loc[e.y].tdom;
-                    const int m1 = nca(sv.loc, tv, e.x);
-                    const int m2 = nca(sv.loc, tv, sv.loc[e.y].par0);
-                    const int mm = min(m1, m2);
-                    if (mm < tv)
-                        __hip_atomic_fetch_min(&sv.loc[e.y].csz, mm, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-                __syncthreads();
-                for (int x = tid; x < nX; x += B) {
-                    const int v = sv.extra[x].y;
-                    const int nv = sv.loc[v].csz;
-                    if (nv != sv.loc[v].tdom) {
-                        sv.loc[v].tdom = nv;
-                        sh.changed = 1;
-                    }
-                }
-                __syncthreads();
-                const int ch = sh.changed;
-                __syncthreads();
-                if (!ch) break;
-            }
-            for (int x = tid; x < nX; x += B) sv.loc[sv.extra[x].y].csz = 1;
-            __syncthreads();
-        }
-
-        // Subtree sizes, deepest BFS level first, and the exact accumulation into D.
-        for (int l = L - 1; l >= 1; --l) {
-            const int b0 = sv.lvl[l], b1 = sv.lvl[l + 1];
-            for (int i = b0 + tid; i < b1; i += B) {
+        // A sample of at most kChunk local vertices runs its dominator and subtree steps in
+        // LDS: the frontier arrays are free once the BFS is done, and hold its tentative
+        // dominators, BFS parents and subtree sizes. The steps are those of the global
+        // form below; only where the three arrays live differs.
+        if (L > 1 && nV <= Shared<B>::kChunk) {
+            int *dom = sh.e0, *par = sh.e1, *sz = sh.qpre;
+            for (int i = tid; i < nV; i += B) {
                 const LocalVtx r = sv.loc[i];
-                if (r.tdom != 0)
-                    __hip_atomic_fetch_add(&sv.loc[r.tdom].csz, r.csz, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                // with reach counts in the map, a leaf of the dominator tree adds nothing here
-                const int add = cnt_on ? r.csz - 1 : r.csz;
-                if (add > 0) atomicAdd(&c.D[r.glob], (unsigned long long)add);
+                dom[i] = r.tdom;
+                par[i] = r.par0;
+                sz[i] = 1;
             }
             __syncthreads();
+            if (nX > 0) {
+                for (int x0 = 0; x0 < nX; x0 += B) {
+                    const int x = x0 + tid;
+                    int2 e = make_int2(0, 0);
+                    if (x < nX) {
+                        e = sv.extra[x];
+                        sz[e.y] = dom[e.y];
+                    }
+                    __syncthreads();
+                    if (x < nX) {
+                        const int tv = dom[e.y];
+                        const int mm = min(nca_lds(dom, tv, e.x), nca_lds(dom, tv, par[e.y]));
+                        if (mm < tv) atomicMin(&sz[e.y], mm);
+                    }
+                    __syncthreads();
+                    if (x < nX) dom[e.y] = sz[e.y];
+                    __syncthreads();
+                }
+                for (;;) {
+                    for (int x = tid; x < nX; x += B) {
+                        const int v = sv.extra[x].y;
+                        sz[v] = dom[v];
+                    }
+                    if (tid == 0) sh.changed = 0;
+                    __syncthreads();
+                    for (int x = tid; x < nX; x += B) {
+                        const int2 e = sv.extra[x];
+                        const int tv = dom[e.y];
+                        const int mm = min(nca_lds(dom, tv, e.x), nca_lds(dom, tv, par[e.y]));
+                        if (mm < tv) atomicMin(&sz[e.y], mm);
+                    }
+                    __syncthreads();
+                    for (int x = tid; x < nX; x += B) {
+                        const int v = sv.extra[x].y;
+                        const int nv = sz[v];
+                        if (nv != dom[v]) {
+                            dom[v] = nv;
+                            sh.changed = 1;
+                        }
+                    }
+                    __syncthreads();
+                    const int ch = sh.changed;
+                    __syncthreads();
+                    if (!ch) break;
+                }
+                for (int x = tid; x < nX; x += B) sz[sv.extra[x].y] = 1;
+                __syncthreads();
+            }
+            for (int l = L - 1; l >= 1; --l) {
+                const int b0 = sv.lvl[l], b1 = sv.lvl[l + 1];
+                for (int i = b0 + tid; i < b1; i += B) {
+                    const int t = dom[i];
+                    const int size = sz[i];
+                    if (t != 0) atomicAdd(&sz[t], size);
+                    const int add = cnt_on ? size - 1 : size;
+                    if (add > 0) atomicAdd(&c.D[sv.loc[i].glob], (unsigned long long)add);
+                }
+                __syncthreads();
+            }
+        } else {
+            // Dominator tree: Jacobi NCA steps over vertices with several reached predecessors.
+            // The subtree-size field of such a vertex holds the next tentative dominator
+            // meanwhile, and is reset to 1 afterwards.
+            if (nX > 0) {
+                // First one Gauss-Seidel sweep: the extra edges in list order (roughly the BFS
+                // order of their sources), B at a time, each chunk one step over its targets on
+                // the tree the earlier chunks left. A step over some vertices and some of their
+                // predecessors keeps every dominator of v on v's tree path (a dominator of v
+                // dominates each predecessor) and only moves t(v) up, so the Jacobi rounds below
+                // still end at the dominator tree; they just have less left to change.
+                for (int x0 = 0; x0 < nX; x0 += B) {
+                    const int x = x0 + tid;
+                    int2 e = make_int2(0, 0);
+                    if (x < nX) {
+                        e = sv.extra[x];
+                        sv.loc[e.y].csz = sv.loc[e.y].tdom;
+                    }
+                    __syncthreads();
+                    if (x < nX) {
+                        const int tv = sv.loc[e.y].tdom;
+                        const int m1 = nca(sv.loc, tv, e.x);
+                        const int m2 = nca(sv.loc, tv, sv.loc[e.y].par0);
+                        const int mm = min(m1, m2);
+                        if (mm < tv)
+                            __hip_atomic_fetch_min(&sv.loc[e.y].csz, mm, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    __syncthreads();
+                    if (x < nX) sv.loc[e.y].tdom = sv.loc[e.y].csz;
+                    __syncthreads();
+                }
+                for (;;) {
+                    for (int x = tid; x < nX; x += B) {
+                        const int v = sv.extra[x].y;
+                        sv.loc[v].csz = sv.loc[v].tdom;
+                    }
+                    if (tid == 0) sh.changed = 0;
+                    __syncthreads();
+                    for (int x = tid; x < nX; x += B) {
+                        const int2 e = sv.extra[x];
+                        const int tv = sv.loc[e.y].tdom;
+                        const int m1 = nca(sv.loc, tv, e.x);
+                        const int m2 = nca(sv.loc, tv, sv.loc[e.y].par0);
+                        const int mm = min(m1, m2);
+                        if (mm < tv)
+                            __hip_atomic_fetch_min(&sv.loc[e.y].csz, mm, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    __syncthreads();
+                    for (int x = tid; x < nX; x += B) {
+                        const int v = sv.extra[x].y;
+                        const int nv = sv.loc[v].csz;
+                        if (nv != sv.loc[v].tdom) {
+                            sv.loc[v].tdom = nv;
+                            sh.changed = 1;
+                        }
+                    }
+                    __syncthreads();
+                    const int ch = sh.changed;
+                    __syncthreads();
+                    if (!ch) break;
+                }
+                for (int x = tid; x < nX; x += B) sv.loc[sv.extra[x].y].csz = 1;
+                __syncthreads();
+            }
+
+            // Subtree sizes, deepest BFS level first, and the exact accumulation into D.
+            for (int l = L - 1; l >= 1; --l) {
+                const int b0 = sv.lvl[l], b1 = sv.lvl[l + 1];
+                for (int i = b0 + tid; i < b1; i += B) {
+                    const LocalVtx r = sv.loc[i];
+                    if (r.tdom != 0)
+                        __hip_atomic_fetch_add(&sv.loc[r.tdom].csz, r.csz, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    // with reach counts in the map, a leaf of the dominator tree adds nothing here
+                    const int add = cnt_on ? r.csz - 1 : r.csz;
+                    if (add > 0) atomicAdd(&c.D[r.glob], (unsigned long long)add);
+                }
+                __syncthreads();
+            }
         }
         if (tid == 0) {
             atomicAdd(&c.stats[0], 1ull);
