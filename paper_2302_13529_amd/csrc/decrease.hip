@@ -93,9 +93,21 @@ constexpr int kPerThread = 4;
 template <int B>
 struct Shared {
     static constexpr int kChunk = B * kPerThread;
-    int e0[kChunk];
-    int e1[kChunk];
-    int qpre[kChunk + 1];
+    // local vertices whose dominator and subtree steps fit the frontier arrays' space
+    static constexpr int kLdsV = kChunk + kChunk / 2;
+    static_assert(kLdsV <= 65536, "16-bit local ids");
+    union {
+        struct {  // the BFS: one frontier chunk
+            int e0[kChunk];
+            int e1[kChunk];
+            int qpre[kChunk + 1];
+        };
+        struct {  // afterwards, a sample of at most kLdsV local vertices
+            int sz[kLdsV];         // subtree sizes (the Jacobi steps' next dominator meanwhile)
+            uint16_t dom[kLdsV];   // tentative immediate dominators
+            uint16_t par[kLdsV];   // BFS parents
+        };
+    };
     int wave[B / 64];
     unsigned idx;
     int tail;
@@ -307,7 +319,7 @@ __device__ __forceinline__ int nca(const LocalVtx *t, int x, int y)
 }
 
 // The same walk over tentative dominators held in LDS.
-__device__ __forceinline__ int nca_lds(const int *dom, int x, int y)
+__device__ __forceinline__ int nca_lds(const uint16_t *dom, int x, int y)
 {
     while (x != y) {
         if (x > y) x = dom[x];
@@ -447,16 +459,18 @@ void decrease_kernel(DecreaseArgs a)
         }
         __syncthreads();
 
-        // A sample of at most kChunk local vertices runs its dominator and subtree steps in
-        // LDS: the frontier arrays are free once the BFS is done, and hold its tentative
-        // dominators, BFS parents and subtree sizes. The steps are those of the global
-        // form below; only where the three arrays live differs.
-        if (L > 1 && nV <= Shared<B>::kChunk) {
-            int *dom = sh.e0, *par = sh.e1, *sz = sh.qpre;
+        // A sample of at most kLdsV local vertices runs its dominator and subtree steps in
+        // LDS: the frontier arrays' space is free once the BFS is done, and holds its
+        // tentative dominators and BFS parents (16-bit local ids) and its subtree sizes. The
+        // steps are those of the global form below; only where the three arrays live
+        // differs.
+        if (L > 1 && nV <= Shared<B>::kLdsV) {
+            uint16_t *dom = sh.dom, *par = sh.par;
+            int *sz = sh.sz;
             for (int i = tid; i < nV; i += B) {
                 const LocalVtx r = sv.loc[i];
-                dom[i] = r.tdom;
-                par[i] = r.par0;
+                dom[i] = (uint16_t)r.tdom;
+                par[i] = (uint16_t)r.par0;
                 sz[i] = 1;
             }
             __syncthreads();
@@ -475,7 +489,7 @@ void decrease_kernel(DecreaseArgs a)
                         if (mm < tv) atomicMin(&sz[e.y], mm);
                     }
                     __syncthreads();
-                    if (x < nX) dom[e.y] = sz[e.y];
+                    if (x < nX) dom[e.y] = (uint16_t)sz[e.y];
                     __syncthreads();
                 }
                 for (;;) {
@@ -496,7 +510,7 @@ void decrease_kernel(DecreaseArgs a)
                         const int v = sv.extra[x].y;
                         const int nv = sz[v];
                         if (nv != dom[v]) {
-                            dom[v] = nv;
+                            dom[v] = (uint16_t)nv;
                             sh.changed = 1;
                         }
                     }
