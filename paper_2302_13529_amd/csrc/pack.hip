@@ -6,7 +6,8 @@
 // of kPackG consecutive samples of one instance side by side:
 //   * the seed level comes from the register seed cache (every sample of an instance
 //     expands the same seed rows; only the coins differ), each lane deciding its cached quads
-//     for every sample of the batch (Definition 4, Philox4x32-10 per 4-edge quad);
+//     for every sample of the batch (Definition 4, Philox4x32-10 per 4-edge quad); seed
+//     rows beyond the cache are expanded from memory like a deeper level;
 //   * deeper BFS levels form one flat work list over the frontiers of all samples of the
 //     batch, and lanes take consecutive edge quads of it, each with its own sample's coins;
 //   * a live edge is claimed in its sample's LDS hash table with one compare-and-swap: all
@@ -151,6 +152,61 @@ __device__ __forceinline__ int pnca(const PackSample &S, int x, int y, int &bad)
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// One chunk of up to 64 frontier entries, one per lane: edge range [e0, e1) and tag
+// (sample << 16) | source local id. Its edge quads are spread over the lanes, two in flight
+// per lane, each with its own sample's coins, and the live edges are claimed.
+__device__ __forceinline__ void expand_chunk(const InstanceDesc &I, PackWave &pw, int e0, int e1,
+                                             int tag, int cnt, uint32_t j0, uint32_t key_lo,
+                                             uint32_t key_hi, uint32_t (&live)[G])
+{
+    const int lane = lane_id();
+    const int nq = quads_of(e0, e1);
+    const int incl = wave_scan(nq);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    pw.e0[lane] = e0;
+    pw.e1[lane] = e1;
+    pw.ex[lane] = incl - nq;
+    pw.tag[lane] = tag;
+    wave_sync();
+    // two quads per lane in flight: both loads issued before either is used
+    for (int qb = 0; qb < total; qb += 128) {
+        int g[2], src[2];
+        uint32_t mask[2];
+        uint4 col[2];
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+            const int q = qb + 64 * h2 + lane;
+            mask[h2] = 0;
+            col[h2] = make_uint4(0, 0, 0, 0);
+            g[h2] = 0;
+            src[h2] = 0;
+            if (q < total) {
+                int l = 0, h = cnt - 1;
+                while (l < h) {
+                    const int mid = (l + h + 1) >> 1;
+                    if (pw.ex[mid] <= q) l = mid;
+                    else h = mid - 1;
+                }
+                const int tg = pw.tag[l];
+                g[h2] = tg >> 16;
+                src[h2] = tg & 0xFFFF;
+                if (pw.s[g[h2]].ovf == 0) {
+                    const int quad = (pw.e0[l] >> 2) + (q - pw.ex[l]);
+                    const uint4 thr = I.thr4[quad];
+                    col[h2] = I.col4[quad];
+                    mask[h2] = live_mask(quad, j0 + (uint32_t)g[h2], key_lo, key_hi, pw.e0[l],
+                                         pw.e1[l], thr);
+                }
+            }
+        }
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+            add_at(live, g[h2], (uint32_t)__builtin_popcount(mask[h2]));
+            claim_mask(pw.s[g[h2]], mask[h2], col[h2], src[h2]);
+        }
+    }
+}
+
 // Samples j0 .. j0 + k - 1 of instance I (k <= G). Returns the bit mask of the samples that
 // finished; the others are to be handed over.
 __device__ uint32_t run_batch(const PackArgs &a, const InstanceDesc &I, const SeedCache &sc,
@@ -205,6 +261,29 @@ __device__ uint32_t run_batch(const PackArgs &a, const InstanceDesc &I, const Se
     }
     wave_sync();
 
+    // Seed level from memory when the seed rows do not fit the register cache: one flat
+    // frontier of (sample, seed) entries whose source is the merged seed (local id 0). The
+    // seeds' out-edges are already counted in sc.scanned, and no seed row is too heavy to
+    // expand here (the rows are the same for every sample).
+    if (sc.total < 0) {
+        const int ns = I.nseeds;
+        const int T = k * ns;
+        for (int base = 0; base < T; base += 64) {
+            wave_sync();
+            const int kk = base + lane;
+            int e0 = 0, e1 = 0, tag = 0;
+            if (kk < T) {
+                const int g = kk / ns;
+                const int v = I.seeds[kk - g * ns];
+                e0 = I.row_ptr[v];
+                e1 = I.row_ptr[v + 1];
+                tag = g << 16;
+            }
+            expand_chunk(I, pw, e0, e1, tag, min(64, T - base), j0, key_lo, key_hi, live);
+        }
+        wave_sync();
+    }
+
     // Deeper levels: one flat frontier over the batch.
     int flo[G], fhi[G], L[G];
     bool act[G];
@@ -249,52 +328,7 @@ __device__ uint32_t run_batch(const PackArgs &a, const InstanceDesc &I, const Se
                     e1 = e0;
                 }
             }
-            const int nq = quads_of(e0, e1);
-            const int incl = wave_scan(nq);
-            const int total = __builtin_amdgcn_readlane(incl, 63);
-            pw.e0[lane] = e0;
-            pw.e1[lane] = e1;
-            pw.ex[lane] = incl - nq;
-            pw.tag[lane] = tag;
-            wave_sync();
-            const int cnt = min(64, T - base);
-            // two quads per lane in flight: both loads issued before either is used
-            for (int qb = 0; qb < total; qb += 128) {
-                int g[2], src[2];
-                uint32_t mask[2];
-                uint4 col[2];
-#pragma unroll
-                for (int h2 = 0; h2 < 2; ++h2) {
-                    const int q = qb + 64 * h2 + lane;
-                    mask[h2] = 0;
-                    col[h2] = make_uint4(0, 0, 0, 0);
-                    g[h2] = 0;
-                    src[h2] = 0;
-                    if (q < total) {
-                        int l = 0, h = cnt - 1;
-                        while (l < h) {
-                            const int mid = (l + h + 1) >> 1;
-                            if (pw.ex[mid] <= q) l = mid;
-                            else h = mid - 1;
-                        }
-                        const int tg = pw.tag[l];
-                        g[h2] = tg >> 16;
-                        src[h2] = tg & 0xFFFF;
-                        if (pw.s[g[h2]].ovf == 0) {
-                            const int quad = (pw.e0[l] >> 2) + (q - pw.ex[l]);
-                            const uint4 thr = I.thr4[quad];
-                            col[h2] = I.col4[quad];
-                            mask[h2] = live_mask(quad, j0 + (uint32_t)g[h2], key_lo, key_hi,
-                                                 pw.e0[l], pw.e1[l], thr);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int h2 = 0; h2 < 2; ++h2) {
-                    add_at(live, g[h2], (uint32_t)__builtin_popcount(mask[h2]));
-                    claim_mask(pw.s[g[h2]], mask[h2], col[h2], src[h2]);
-                }
-            }
+            expand_chunk(I, pw, e0, e1, tag, min(64, T - base), j0, key_lo, key_hi, live);
         }
         wave_sync();
 #pragma unroll
@@ -506,8 +540,8 @@ __global__ __launch_bounds__(kPackBlock) void decrease_pack_kernel(PackArgs a)
                 cur_lo = I.sample_base;
                 cur_hi = I.sample_base + I.theta;
                 // An instance whose samples mostly outgrew this kernel in an earlier round
-                // skips it (control word set by the round's argmax); so does one whose seed
-                // rows do not fit the register cache.
+                // skips it (control word set by the round's argmax). Seed rows that do not
+                // fit the register cache are expanded from memory instead.
                 skip = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
                            &I.ctrl[kCtrlSkipPack], __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT)) != 0u;
@@ -518,7 +552,6 @@ __global__ __launch_bounds__(kPackBlock) void decrease_pack_kernel(PackArgs a)
                     sc.total = -1;
                 } else if (!skip) {
                     build_seed_cache(I, pw.e0, pw.e1, pw.ex, sc);
-                    skip = sc.total < 0;
                 } else {
                     sc.total = -1;
                 }
