@@ -77,6 +77,31 @@ def test_lt_rmat17(gpu):
     g.close()
 
 
+def test_lt_rmat22_full_size(gpu):
+    """The 4M-vertex graph under LT: a few samples exactly against the checker, then the full
+    theta launch (the benchmark's LT configuration) against properties that hold at any size."""
+    case("generating rmat22 (4M vertices, 35M edges)")
+    t = H.cached("rmat22", gg.large_plain)
+    g = gpu.Graph(t.row_ptr, t.col, t.prob, model=gpu.IMIN_LT)
+    check(g, t.n, t.row_ptr, t.col, t.prob, t.seeds, None, 3, 0, "rmat22")
+    case("rmat22 LT full theta")
+    D, st = g.decrease(t.seeds, None, t.theta, 0)
+    assert st["samples"] == t.theta and st["spilled"] == 0
+    assert st["live_edges"] == st["reached"]
+    assert np.all(D[t.seeds] == 0)
+    assert int(D.sum()) >= st["reached"]
+    # each vertex draws its trigger edge from its own coins, so blocking u changes no other
+    # vertex's choice and removes exactly the D[u] reached vertices u dominates (Corollary 1)
+    for u in [int(u) for u in np.argsort(-D.astype(np.int64))[:2]]:
+        blk = np.zeros(t.n, np.uint8)
+        blk[u] = 1
+        case(f"rmat22 LT full theta, blocked {u}")
+        D2, st2 = g.decrease(t.seeds, blk, t.theta, 0)
+        assert st2["reached"] == st["reached"] - int(D[u])
+        assert D2[u] == 0
+    g.close()
+
+
 def test_lt_batch_and_server(gpu):
     insts = gg.batched_instances(count=6, seed=9)
     # TR probabilities (at most 0.1 each) are not LT weights; use 1/indeg instead
