@@ -364,9 +364,10 @@ IMIN_API int imin_server_result(imin_server *s, uint64_t ticket, int32_t *blocke
  * Limits: the graph's scratch must fit the array -- per workgroup slot about 30 * (n + 1)
  * bytes (38 * (n + 1) under IC, whose slots also keep each reached vertex's row range),
  * plus two large-capacity slots of about that much plus 8 * m bytes when a slot's
- * extra-edge list cannot hold m edges, plus 8 * theta + 9 * n bytes of lists and marks --
- * else IMIN_ERANGE (for example a 2^17-vertex, 10^6-edge graph fits; a 2^22-vertex one does
- * not). Fewer slots than imin_decrease uses may fit, which costs speed, never results.
+ * extra-edge list cannot hold m edges, plus 8 * theta + 8 * nS bytes of lists and n / 8 + n
+ * bytes of seed bits and blocked marks -- else IMIN_ERANGE (for example a 2^17-vertex,
+ * 10^6-edge graph fits; a 2^22-vertex one does not). Fewer slots than imin_decrease uses
+ * may fit, which costs speed, never results.
  * Every call on one GPU shares that GPU's array, so calls that overlap on one GPU race;
  * the call clears what must start at zero and leaves the graph's thresholds as created.
  * Errors: IMIN_EINVAL (as imin_decrease, or d_counts NULL), IMIN_ERANGE, IMIN_EDEVICE.
