@@ -50,7 +50,7 @@ enum {
     IMIN_EINVAL = -1,  /* an argument violates the contract stated at the call */
     IMIN_ENOMEM = -2,  /* host or device memory could not be allocated */
     IMIN_EDEVICE = -3, /* no usable GPU, or a HIP call failed */
-    IMIN_ERANGE = -4   /* a size exceeds what the library supports (e.g. m >= 2^31) */
+    IMIN_ERANGE = -4   /* a size exceeds what the library supports (e.g. theta > 2^31) */
 };
 
 /* Propagation models for imin_graph_create_model. */
@@ -94,8 +94,9 @@ typedef struct {
 
 /*
  * imin_graph_create -- validate a graph and make it resident on the current HIP device.
- *   n        number of vertices, n >= 1.
- *   m        number of edges, 0 <= m < 2^31; must equal row_ptr[n].
+ *   n        number of vertices, 1 <= n < 2^31 - 1 (IMIN_ERANGE for n = 2^31 - 1, whose
+ *            row_ptr would have 2^31 entries).
+ *   m        number of edges, m >= 0; must equal row_ptr[n].
  *   row_ptr  host int32[n+1], row_ptr[0] = 0, non-decreasing.
  *   col      host int32[m], every entry in [0, n). May be NULL when m = 0.
  *   prob     host float[m], the propagation probability p(u,v) of each edge (Section III-A),
@@ -105,7 +106,7 @@ typedef struct {
  * The probabilities are turned into 24-bit thresholds ceil(p * 2^24) on the host; the
  * device never does floating-point arithmetic on them.
  * Errors: IMIN_EINVAL for any violation above (out is then untouched), IMIN_ERANGE for
- * m >= 2^31, IMIN_ENOMEM, IMIN_EDEVICE.
+ * n = 2^31 - 1, IMIN_ENOMEM, IMIN_EDEVICE.
  */
 IMIN_API int imin_graph_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col,
                       const float *prob, imin_graph **out);
@@ -141,8 +142,8 @@ IMIN_API void imin_graph_destroy(imin_graph *g);
  *   seed     the Philox key k of this call.
  *   counts   host uint64[n], receives D[u]; 0 for seeds, blocked and never-reached vertices.
  *   stats    optional (may be NULL), receives the work counters.
- * Errors: IMIN_EINVAL (bad seed, seed blocked, theta = 0, NULL g/S/counts), IMIN_ENOMEM,
- * IMIN_EDEVICE.
+ * Errors: IMIN_EINVAL (bad seed, seed blocked, theta = 0, NULL g/S/counts), IMIN_ERANGE
+ * (theta > 2^31), IMIN_ENOMEM, IMIN_EDEVICE.
  */
 IMIN_API int imin_decrease(imin_graph *g, const int32_t *S, int32_t nS, const uint8_t *blocked,
                   uint32_t theta, uint64_t seed, uint64_t *counts, imin_stats *stats);
@@ -176,8 +177,8 @@ IMIN_API int imin_spread(imin_graph *g, const int32_t *S, int32_t nS, const uint
  *       argmax over the remaining CB; then, for each chosen blocker u in reverse insertion
  *       order (over a snapshot of that order), u is unblocked, D is re-estimated, the argmax
  *       x over V \ (S u B) takes u's slot, and the pass stops at the first x == u.
- * Errors: IMIN_EINVAL (as imin_decrease, b < 0, unknown mode, NULL outputs), IMIN_ENOMEM,
- * IMIN_EDEVICE.
+ * Errors: IMIN_EINVAL (as imin_decrease, b < 0, unknown mode, NULL outputs), IMIN_ERANGE
+ * (theta > 2^31), IMIN_ENOMEM, IMIN_EDEVICE.
  */
 IMIN_API int imin_greedy(imin_graph *g, const int32_t *S, int32_t nS, int32_t b, uint32_t theta,
                 uint64_t seed, int mode, int32_t *blockers, int32_t *n_blockers,

@@ -69,6 +69,22 @@ def test_graph_create_rejects_invalid(case):
     assert h.value is None
 
 
+def test_graph_create_range_and_model_checks_come_first():
+    """n = 2^31 - 1 (row_ptr would need 2^31 entries) is rejected with IMIN_ERANGE before
+    row_ptr is read, and an unknown model with IMIN_EINVAL, both before any device call."""
+    lib = binding.load()
+    row_ptr = np.zeros(2, np.int32)
+    h = ctypes.c_void_p()
+    rc = lib.imin_graph_create(2**31 - 1, 0, row_ptr.ctypes.data_as(ctypes.c_void_p), None,
+                               None, ctypes.byref(h))
+    assert rc == binding.IMIN_ERANGE and h.value is None
+    row_ptr = np.array([0, 0], np.int32)
+    for model in (-1, 2, 7):
+        rc = lib.imin_graph_create_model(1, 0, row_ptr.ctypes.data_as(ctypes.c_void_p), None,
+                                         None, model, ctypes.byref(h))
+        assert rc == binding.IMIN_EINVAL and h.value is None
+
+
 def test_null_handle_is_rejected():
     lib = binding.load()
     D = np.zeros(4, np.uint64)
