@@ -289,7 +289,8 @@ typedef struct {
     int32_t max_active;   /* most queries admitted at once (0: 256) */
     uint32_t max_theta;   /* largest theta a query may ask for (0: 65536); max_active *
                              max_theta must not exceed 2^31 (IMIN_ERANGE) */
-    imin_launch launch;   /* wave-kernel launch shape (zeros: defaults) */
+    imin_launch launch;   /* wavefront-level kernels' launch shape, as for imin_greedy_batch
+                             (zeros: defaults; its graph field is not used) */
 } imin_server_config;
 
 /*
