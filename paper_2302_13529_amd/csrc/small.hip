@@ -50,26 +50,32 @@ struct SmallShared {
 };
 
 // Per-lane copy of the reached vertex ids: lane l holds local ids l, 64+l, 128+l, 192+l.
+// Four named registers rather than an array: the compiler turns a write to row id >> 6 of an
+// array into a store at a run-time index, which puts the whole array in scratch memory.
+static_assert(kSmallV == 4 * 64, "the mirror holds four rows of 64 local ids");
 struct Mirror {
-    int g[kSmallV / 64];
+    int g0 = -1, g1 = -1, g2 = -1, g3 = -1;
 };
 
 __device__ __forceinline__ void mirror_set(Mirror &m, int id, int v)
 {
-    if (lane_id() == (id & 63)) {
-#pragma unroll
-        for (int r = 0; r < kSmallV / 64; ++r)
-            if ((id >> 6) == r) m.g[r] = v;
-    }
+    const bool mine = lane_id() == (id & 63);
+    const int r = id >> 6;
+    m.g0 = (mine && r == 0) ? v : m.g0;
+    m.g1 = (mine && r == 1) ? v : m.g1;
+    m.g2 = (mine && r == 2) ? v : m.g2;
+    m.g3 = (mine && r == 3) ? v : m.g3;
 }
 
 // Local id of vertex c (uniform across the wave), or -1.
 __device__ __forceinline__ int mirror_find(const Mirror &m, int c)
 {
+    const int lane = lane_id();
     int hit = -1;
-#pragma unroll
-    for (int r = 0; r < kSmallV / 64; ++r)
-        if (m.g[r] == c) hit = r * 64 + lane_id();
+    hit = m.g0 == c ? lane : hit;
+    hit = m.g1 == c ? 64 + lane : hit;
+    hit = m.g2 == c ? 128 + lane : hit;
+    hit = m.g3 == c ? 192 + lane : hit;
     const unsigned long long b = __ballot(hit >= 0);
     if (!b) return -1;
     return __builtin_amdgcn_readlane(hit, (int)__builtin_ctzll(b));
@@ -236,9 +242,7 @@ __device__ bool run_sample(const SmallArgs &a, const InstanceDesc &I, const Seed
     const int lane = lane_id();
     const unsigned long long key = (((unsigned long long)I.seed_hi << 32) | I.seed_lo) + a.round;
     const uint32_t key_lo = (uint32_t)key, key_hi = (uint32_t)(key >> 32);
-    Mirror m;
-#pragma unroll
-    for (int r = 0; r < kSmallV / 64; ++r) m.g[r] = -1;
+    Mirror m;  // every row -1: nothing reached yet
     SampleCtx cx;
     cx.nV = 1;
     cx.nX = 0;
