@@ -57,7 +57,7 @@ struct imin_graph {
                                              // round (wave kernel on), 2 = the next round is a
                                              // timed trial without it, 3 = compare; 0 = none
     size_t probe_kev[2] = {0, 0};            // kev index of the timed rounds (with, without)
-    imin_launch small_launch{0, 0, 0};       // 0 fields: defaults
+    imin_launch small_launch{};              // 0 fields: defaults
     uint32_t *d_ovf = nullptr;
     uint32_t ovf_cap = 0;
     unsigned long long *d_part_d = nullptr;

@@ -42,7 +42,7 @@ __device__ void block_best(unsigned long long &bd, int &bi)
     si[threadIdx.x] = bi;
     __syncthreads();
     for (int s = kSelBlock / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
+        if ((int)threadIdx.x < s) {
             unsigned long long d = sd[threadIdx.x];
             int i = si[threadIdx.x];
             better(d, i, sd[threadIdx.x + s], si[threadIdx.x + s]);
