@@ -31,12 +31,17 @@ def build() -> str:
 
 
 def _load():
+    """The checker library: the build next to the source (rebuilt when older than it), or,
+    when IMIN_ORACLE_LIB names a file, that build of the same source as it is (the
+    sanitizer builds of ``sanitize.sh``)."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    path = os.environ.get("IMIN_ORACLE_LIB") or _LIB
+    if path == _LIB and (not os.path.exists(_LIB) or
+                         os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
         build()
-    lib = ctypes.CDLL(_LIB)
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     lib.orc_philox4x32_10.argtypes = [P, P, P]
     lib.orc_philox4x32_10.restype = None
