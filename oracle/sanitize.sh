@@ -4,6 +4,7 @@
 # ThreadSanitizer, into a temporary directory, and runs the checker's pin tests against each
 # build (IMIN_ORACLE_LIB selects the build; the sanitizer runtime is preloaded into Python).
 # The threaded form of the checker (samples split over host threads) runs under both.
+# PYTHON names the interpreter (default python3).
 set -euo pipefail
 ROOT=$(cd "$(dirname "$0")/.." && pwd)
 T=$(mktemp -d)
@@ -19,8 +20,8 @@ PINS=(tests/test_oracle_pins.py tests/test_oracle_greedy.py tests/test_oracle_lt
 echo "[sanitize] address + undefined behaviour"
 IMIN_ORACLE_LIB="$T/asan_ubsan.so" LD_PRELOAD="$(gcc -print-file-name=libasan.so)" \
     ASAN_OPTIONS=detect_leaks=0:abort_on_error=1 UBSAN_OPTIONS=halt_on_error=1:print_stacktrace=1 \
-    python -m pytest -q -x -s -p no:cacheprovider "${PINS[@]}"
+    "${PYTHON:-python3}" -m pytest -q -x -s -p no:cacheprovider "${PINS[@]}"
 echo "[sanitize] threads"
 IMIN_ORACLE_LIB="$T/tsan.so" LD_PRELOAD="$(gcc -print-file-name=libtsan.so)" \
     TSAN_OPTIONS=halt_on_error=1 \
-    python -m pytest -q -x -s -p no:cacheprovider tests/test_oracle_counters_threads.py
+    "${PYTHON:-python3}" -m pytest -q -x -s -p no:cacheprovider tests/test_oracle_counters_threads.py

@@ -7,6 +7,7 @@ the checker (including its threaded form) aborts the run and fails this test.
 import os
 import shutil
 import subprocess
+import sys
 
 import pytest
 
@@ -25,7 +26,8 @@ def _runtime(name):
 @pytest.mark.skipif(not (_runtime("libasan.so") and _runtime("libtsan.so")),
                     reason="gcc sanitizer runtimes not available")
 def test_checker_is_clean_under_sanitizers():
+    env = dict(os.environ, PYTHON=sys.executable)
     res = subprocess.run(["bash", SCRIPT], capture_output=True, text=True, timeout=900,
-                         cwd=ROOT)
+                         cwd=ROOT, env=env)
     assert res.returncode == 0, (res.stdout[-3000:], res.stderr[-3000:])
     assert res.stdout.count(" passed") == 2, res.stdout[-2000:]
