@@ -13,13 +13,13 @@ The default line also carries two sub-objects:
 * "served": the 2^20-vertex R-MAT graph resident and the 2,000-query mix, saturated
   (samples/s against plain calls on a prefix), then a prefix under Poisson arrivals (p50 /
   p99 latency).
-Each carries "verified": its blockers and work counters against the CPU checker's stored
+Each carries "verified": its blockers and work counters against the CPU oracle's stored
 results at that configuration (tests/golden).
 
 Inputs are seeded synthetic data resident in HBM before the timed region starts. Prints
 one JSON line: samples/s over the timed steps, the roofline figure of the dominant kernel
 (algorithmic bytes per launch over its average launch time, against MI355X's 8 TB/s HBM
-peak), and the CPU checker timed on a bounded sample of the same workload.
+peak), and the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -49,7 +49,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
 def golden(name: str) -> dict:
-    """A stored result of the CPU checker at a benchmark configuration (tests/golden), read
+    """A stored result of the CPU oracle at a benchmark configuration (tests/golden), read
     as text: blocker lists and work counters to compare the GPU's results with."""
     sys.path.insert(0, ROOT)
     from tests import helpers
@@ -83,7 +83,7 @@ def traffic_from_profile(path: str, kernel_source: str):
 
 
 def cpu_workers() -> int:
-    """Host cores the CPU checker runs on: this process's CPU affinity, at most 16."""
+    """Host cores the CPU oracle runs on: this process's CPU affinity, at most 16."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -91,12 +91,12 @@ def cpu_workers() -> int:
     return max(1, min(16, n))
 
 
-# What the forked checker processes work on; set before the pool forks, read in the workers.
+# What the forked oracle processes work on; set before the pool forks, read in the workers.
 _CPU_JOB: dict = {}
 
 
 def _cpu_samples(js) -> tuple:
-    """Samples js of greedy round 0 (key 0, no blockers) through the checker's one-sample
+    """Samples js of greedy round 0 (key 0, no blockers) through the oracle's one-sample
     call, subtree sizes accumulated into counts as its decrease call does."""
     import numpy as np
     from oracle import oracle as orc
@@ -123,7 +123,7 @@ def _cpu_instances(ks) -> int:
 
 
 def _parallel(fn, parts):
-    """fn over parts in forked processes (one per part, the checker unchanged); returns the
+    """fn over parts in forked processes (one per part, the oracle unchanged); returns the
     results and the wall time of the work alone. Must run before this process touches the
     GPU."""
     import multiprocessing as mp
@@ -137,7 +137,7 @@ def _parallel(fn, parts):
 
 
 def cpu_baseline(inst, theta_sample: int, model: str = "ic") -> dict:
-    """The checker on samples 0..theta_sample-1 of greedy round 0, spread over the host
+    """The oracle on samples 0..theta_sample-1 of greedy round 0, spread over the host
     cores (each process takes every k-th sample)."""
     from oracle import oracle as orc
     cores = min(cpu_workers(), theta_sample)
@@ -147,12 +147,12 @@ def cpu_baseline(inst, theta_sample: int, model: str = "ic") -> dict:
     done = sum(k for _, k in res)
     return {"value": done / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
             "sample": f"{done} of the {inst.theta} samples of greedy round 0 "
-                      f"(no blockers, key 0) on {inst.name}, C checker in {cores} processes "
+                      f"(no blockers, key 0) on {inst.name}, C oracle in {cores} processes "
                       f"(every {cores}-th sample each), {dt:.1f} s"}
 
 
 def batched_cpu_baseline(insts) -> dict:
-    """The checker on round 0 (full theta) of every batched instance, in forked processes;
+    """The oracle on round 0 (full theta) of every batched instance, in forked processes;
     call it before this process touches the GPU."""
     print("[bench] cpu baseline (batched instances)", file=sys.stderr, flush=True)
     cores = cpu_workers()
@@ -160,14 +160,14 @@ def batched_cpu_baseline(insts) -> dict:
     res, cdt = _parallel(_cpu_instances, [list(range(w, len(insts), cores))
                                           for w in range(cores)])
     return {"value": sum(res) / cdt, "unit": "samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"round 0 (full theta) of all {len(insts)} instances, C checker in "
+            "sample": f"round 0 (full theta) of all {len(insts)} instances, C oracle in "
                       f"{cores} processes (every {cores}-th instance each), {cdt:.1f} s"}
 
 
 def bench_batched(args, with_cpu: bool, insts=None, cpu=None) -> dict:
     """256 Chung-Lu instances: every instance as a plain imin_greedy call, then args.steps
-    batched calls over all of them; blockers compared with each other and with the checker's
-    stored results. `insts` and `cpu` may come from an earlier generation and checker run."""
+    batched calls over all of them; blockers compared with each other and with the oracle's
+    stored results. `insts` and `cpu` may come from an earlier generation and oracle run."""
     import torch
     from paper_2302_13529_amd import binding, graphgen as gg
 
@@ -175,7 +175,7 @@ def bench_batched(args, with_cpu: bool, insts=None, cpu=None) -> dict:
         print("[bench] generating 256 batched instances", file=sys.stderr, flush=True)
         insts = gg.batched_instances()
     if with_cpu and cpu is None:
-        # the checker's processes fork before this process touches the GPU
+        # the oracle's processes fork before this process touches the GPU
         cpu = batched_cpu_baseline(insts)
     graphs = [binding.Graph(t.row_ptr, t.col, t.prob) for t in insts]
     probs = [(g.handle, t.seeds, t.b, t.theta, t.seed) for g, t in zip(graphs, insts)]
@@ -354,7 +354,7 @@ def bench_headline(args) -> dict:
     inst = gg.large_plain()
     cpu = None
     if not args.no_cpu:
-        # the checker's processes fork before this process touches the GPU
+        # the oracle's processes fork before this process touches the GPU
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         k = args.cpu_samples if args.model == "ic" else max(1, args.cpu_samples // 8)
         cpu = cpu_baseline(inst, k, args.model)
@@ -414,7 +414,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-samples", type=int, default=256,
-                    help="rmat22: samples the CPU checker times (an eighth of it under LT, whose "
+                    help="rmat22: samples the CPU oracle times (an eighth of it under LT, whose "
                          "samples reach about 3x more vertices)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", choices=["all", "rmat22", "batched", "served"], default="all",
@@ -461,7 +461,7 @@ def main() -> int:
         return 0
     insts = cpu_b = None
     if args.workload == "all":
-        # the batched instances' checker run forks before anything touches the GPU
+        # the batched instances' oracle run forks before anything touches the GPU
         from paper_2302_13529_amd import graphgen as gg
         insts = gg.batched_instances()
         if not args.no_cpu:

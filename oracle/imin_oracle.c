@@ -1,5 +1,5 @@
 /*
- * imin_oracle.c -- plain, single-threaded CPU checker for the live-edge spread-decrease
+ * imin_oracle.c -- plain, single-threaded CPU oracle for the live-edge spread-decrease
  * estimate and the two greedy drivers built on it.
  *
  * TEST INFRASTRUCTURE ONLY. Nothing in the library path may link, load or call this

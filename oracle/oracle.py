@@ -1,4 +1,4 @@
-"""ctypes front end of the CPU checker in ``imin_oracle.c``.
+"""ctypes front end of the CPU oracle in ``imin_oracle.c``.
 
 TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the benchmark's
 CPU-baseline leg, never by the library. ``build()`` compiles the C file with gcc.
@@ -22,7 +22,7 @@ _lib = None
 
 
 def build() -> str:
-    """Compile the checker with gcc (plain C99, -O2) next to its source."""
+    """Compile the oracle with gcc (plain C99, -O2) next to its source."""
     tmp = _LIB + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
                            "-pthread", "-o", tmp, _SRC, "-lm"])
@@ -31,7 +31,7 @@ def build() -> str:
 
 
 def _load():
-    """The checker library: the build next to the source (rebuilt when older than it), or,
+    """The oracle library: the build next to the source (rebuilt when older than it), or,
     when IMIN_ORACLE_LIB names a file, that build of the same source as it is (the
     sanitizer builds of ``sanitize.sh``)."""
     global _lib

@@ -1,9 +1,9 @@
 #!/bin/bash
-# Host-only checks of the CPU checker itself (test infrastructure, never the library): builds
+# Host-only checks of the CPU oracle itself (test infrastructure, never the library): builds
 # imin_oracle.c with gcc under AddressSanitizer + UndefinedBehaviorSanitizer and under
-# ThreadSanitizer, into a temporary directory, and runs the checker's pin tests against each
+# ThreadSanitizer, into a temporary directory, and runs the oracle's pin tests against each
 # build (IMIN_ORACLE_LIB selects the build; the sanitizer runtime is preloaded into Python).
-# The threaded form of the checker (samples split over host threads) runs under both.
+# The threaded form of the oracle (samples split over host threads) runs under both.
 # PYTHON names the interpreter (default python3).
 set -euo pipefail
 ROOT=$(cd "$(dirname "$0")/.." && pwd)

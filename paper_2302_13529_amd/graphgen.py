@@ -11,7 +11,7 @@ of comparable shape, generated from a fixed seed:
   permutation so that vertex id carries no degree information.
 
 This module holds none of the blocking method's arithmetic. It produces only the
-inputs both the library and the checker consume: CSR arrays (int32), float32 edge
+inputs both the library and the oracle consume: CSR arrays (int32), float32 edge
 probabilities and seed lists. Edges inside a CSR row are sorted by target id; the
 edge id of an edge is its CSR position.
 """

@@ -1,6 +1,6 @@
-"""Write the checker's results at the five benchmark configurations as text fixtures.
+"""Write the oracle's results at the five benchmark configurations as text fixtures.
 
-Every value written here comes from ``oracle/`` (the plain CPU checker, its threaded
+Every value written here comes from ``oracle/`` (the plain CPU oracle, its threaded
 variant spreading each Algorithm 2 call's samples over host threads) applied to the seeded
 synthetic inputs of ``paper_2302_13529_amd.graphgen``; nothing is read from the GPU
 library. The GPU tests compare the library's results against these files bit-exactly.
@@ -40,7 +40,7 @@ C5_SUBSET_SIZE = 20
 
 
 def c5_subset(count: int = 2000):
-    """The indices of the served queries checked against the checker (sorted)."""
+    """The indices of the served queries checked against the oracle (sorted)."""
     rng = np.random.default_rng(C5_SUBSET_SEED)
     return sorted(int(i) for i in rng.choice(count, size=C5_SUBSET_SIZE, replace=False))
 

@@ -281,7 +281,7 @@ def _star_graph(leaves, p):
 def test_packed_kernel_capacity_edges(gpu):
     """Batched instances whose samples sit on either side of the packed kernel's limits
     (63 reached vertices, 64 non-tree live edges, 256 edge quads of one frontier vertex):
-    each result must equal the plain call and the checker, and the samples that fit must
+    each result must equal the plain call and the oracle, and the samples that fit must
     have been finished by the packed kernel."""
     cases = []
     # certain paths: 63 reached vertices fit exactly, 64 are handed over

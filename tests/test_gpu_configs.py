@@ -1,6 +1,6 @@
-"""Blocker sets and counters at the five benchmark configurations, against the checker.
+"""Blocker sets and counters at the five benchmark configurations, against the oracle.
 
-The expected values are the checker's own full runs at each configuration's stated sizes
+The expected values are the oracle's own full runs at each configuration's stated sizes
 and budgets (tests/golden/config_*.txt, written by make_config_goldens.py from oracle/
 alone): the library must reproduce every blocker, in order, and every work counter
 bit-exactly.
@@ -115,7 +115,7 @@ def test_served_subset_full_budgets(gpu):
 def test_rmat17_greedy_replace_batched_and_served(gpu):
     """GreedyReplace at b = 100, theta = 10^4 on the 2^17-vertex R-MAT graph through the
     batched call (a batch with a second, smaller instance) and through the server, against
-    the checker's full run."""
+    the oracle's full run."""
     want = H.read_config_golden("config_c2_gr.txt")
     t = H.cached("rmat17", gg.rmat_plain)
     g = gpu.Graph(t.row_ptr, t.col, t.prob)

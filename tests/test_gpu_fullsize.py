@@ -1,8 +1,8 @@
 """The served form and the 2^17-vertex R-MAT graph at their full input sizes, against the
-checker run live (the stored full-budget results are in test_gpu_configs.py).
+oracle run live (the stored full-budget results are in test_gpu_configs.py).
 
 C5: the 1M-vertex R-MAT graph with a mix of queries in the server, each against the
-checker. C2: one Algorithm 2 call at theta = 10^4, every count against the checker.
+oracle. C2: one Algorithm 2 call at theta = 10^4, every count against the oracle.
 """
 import numpy as np
 import pytest
@@ -21,7 +21,7 @@ def test_served_graph_full_size(gpu):
     case("generating the served graph (2^20 vertices, 8M edges)")
     inst = gg.served_graph()
     qs = gg.served_queries(inst.n, count=20, seed=6)
-    # the first queries of the mix, with budgets and samples cut so the checker keeps up
+    # the first queries of the mix, with budgets and samples cut so the oracle keeps up
     mix = [dict(seeds=q["seeds"], b=min(q["b"], 3), theta=min(q["theta"], 500), seed=q["seed"])
            for q in qs[:8]]
     g = gpu.Graph(inst.row_ptr, inst.col, inst.prob)
@@ -42,7 +42,7 @@ def test_served_graph_full_size(gpu):
 
 def test_rmat17_full_theta_round(gpu):
     """C2 at full size: one Algorithm 2 call with theta = 10^4 on the 131k-vertex R-MAT graph,
-    every count against the checker (about a minute of checker time)."""
+    every count against the oracle (about a minute of oracle time)."""
     t = gg.rmat_plain()
     g = gpu.Graph(t.row_ptr, t.col, t.prob)
     case("rmat17 decrease, theta 10^4")

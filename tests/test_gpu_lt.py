@@ -1,4 +1,4 @@
-"""Linear-threshold (triggering-model) sampling on the GPU against the checker, bit-exact.
+"""Linear-threshold (triggering-model) sampling on the GPU against the oracle, bit-exact.
 
 Weighted-cascade weights 1/indeg(v) sum to one over every vertex's in-edges, so the same
 synthetic graphs serve as LT inputs (Section V-E).
@@ -78,7 +78,7 @@ def test_lt_rmat17(gpu):
 
 
 def test_lt_rmat22_full_size(gpu):
-    """The 4M-vertex graph under LT: a few samples exactly against the checker, then the full
+    """The 4M-vertex graph under LT: a few samples exactly against the oracle, then the full
     theta launch (the benchmark's LT configuration) against properties that hold at any size."""
     case("generating rmat22 (4M vertices, 35M edges)")
     t = H.cached("rmat22", gg.large_plain)
@@ -152,7 +152,7 @@ def test_lt_weights_validated(gpu):
 
 def test_lt_spread_counts_equal_the_oracle(gpu):
     """Reachability-only sampling (imin_spread) under the linear-threshold model: the reached
-    sum is an integer and must equal the checker's, on every kernel path, with and without
+    sum is an integer and must equal the oracle's, on every kernel path, with and without
     blockers, and equal the counters of the full decrease call."""
     t = gg.tiny_plain()
     g = gpu.Graph(t.row_ptr, t.col, t.prob, model=gpu.IMIN_LT)

@@ -2,7 +2,7 @@
 work counters are the same in two different mixes (all submitted at once with up to 256
 admitted, and in reverse order with up to 48 admitted), and equal a plain imin_greedy call
 alone for a seeded subset of 200 queries (the seeded 20-query subset is checked against the
-checker's full runs in test_gpu_configs.py)."""
+oracle's full runs in test_gpu_configs.py)."""
 import numpy as np
 import pytest
 

@@ -158,7 +158,7 @@ def test_server_degenerate_queries(gpu):
 
 def test_server_greedy_replace_mixed_with_advanced_greedy(gpu):
     """GreedyReplace queries (Algorithm 4) in the server beside AdvancedGreedy ones: each
-    equals imin_greedy alone with its mode, and a few equal the checker."""
+    equals imin_greedy alone with its mode, and a few equal the oracle."""
     t = gg.tiny_plain()
     g = gpu.Graph(t.row_ptr, t.col, t.prob)
     qs = _queries(t.n, 30, 4, bmax=8)

@@ -1,5 +1,5 @@
 """The seeded synthetic inputs match the recipes the benchmark configurations state (sizes,
-probability models, seed rules, query mix), and are reproducible: the stored checker
+probability models, seed rules, query mix), and are reproducible: the stored oracle
 results under tests/golden were made from exactly these inputs."""
 import numpy as np
 

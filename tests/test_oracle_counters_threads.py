@@ -1,4 +1,4 @@
-"""More pins of the checker: its work counters, its linear-threshold interval bounds, and its
+"""More pins of the oracle: its work counters, its linear-threshold interval bounds, and its
 threaded variant.
 
 * Work counters (Algorithm 2's loop over sampled graphs): with every probability 0 or 1

@@ -1,4 +1,4 @@
-"""Pins of the checker's linear-threshold (triggering-model) sampling, Section V-E.
+"""Pins of the oracle's linear-threshold (triggering-model) sampling, Section V-E.
 
 Under LT a vertex keeps at most one in-edge per sample (its triggering set), chosen with
 probability equal to the edge's weight. Pinned here against: closed forms that tell LT from

@@ -1,8 +1,8 @@
-"""The CPU checker under AddressSanitizer + UBSan and ThreadSanitizer (gcc, host only).
+"""The CPU oracle under AddressSanitizer + UBSan and ThreadSanitizer (gcc, host only).
 
-``oracle/sanitize.sh`` builds the checker's C source with each sanitizer and runs its pin
+``oracle/sanitize.sh`` builds the oracle's C source with each sanitizer and runs its pin
 tests against those builds; any out-of-bounds access, undefined behaviour or data race in
-the checker (including its threaded form) aborts the run and fails this test.
+the oracle (including its threaded form) aborts the run and fails this test.
 """
 import os
 import shutil
