@@ -3,6 +3,8 @@ rejects invalid graphs before touching a device (host logic only; no compute cal
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -110,3 +112,21 @@ def test_batch_rejects_null_graph_before_touching_a_device():
     assert lib.imin_greedy_batch(arr, 0, 0, None) == binding.IMIN_EINVAL
     for bad in (binding.imin_launch(-1, 0, 0, 0), binding.imin_launch(0, 0, 0, 2)):
         assert lib.imin_greedy_batch(arr, 1, 0, ctypes.byref(bad)) == binding.IMIN_EINVAL
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_c_program_links_and_checks_arguments(tmp_path):
+    """The C ABI from C: tests/abi_check.c built as strict C99 against the header and the
+    library, then run."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    root = os.path.dirname(here)
+    libdir = os.path.dirname(binding.LIB_PATH)
+    exe = tmp_path / "abi_check"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-Wpedantic", "-Werror",
+                           "-I", os.path.join(root, "include"),
+                           os.path.join(here, "abi_check.c"), "-L", libdir, "-limin",
+                           f"-Wl,-rpath,{libdir}", "-Wl,-rpath-link,/opt/rocm/lib",
+                           "-o", str(exe)])
+    res = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0 and "c abi ok" in res.stdout, (res.returncode, res.stdout,
+                                                              res.stderr)
