@@ -1,6 +1,7 @@
 /*
- * imin_oracle.c -- plain, single-threaded CPU oracle for the live-edge spread-decrease
- * estimate and the two greedy drivers built on it.
+ * imin_oracle.c -- plain CPU oracle for the live-edge spread-decrease estimate and the two
+ * greedy drivers built on it. Each sample is computed by one thread; the _mt entry points
+ * only split a call's independent samples over host threads and add their integer sums.
  *
  * TEST INFRASTRUCTURE ONLY. Nothing in the library path may link, load or call this
  * file; it exists so tests, the smoke check and the benchmark's CPU-baseline leg can
