@@ -41,6 +41,10 @@ def test_committed_profile_names_a_source_hash_and_traffic():
                 fields[k.strip()] = v.split()[0]
     assert len(fields["kernel_source_sha256"]) == 64
     assert float(fields["traffic_bytes_per_launch"]) > float(fields["algorithmic_bytes_per_launch"])
+    # the committed counters belong to the committed kernel source, so the bench line carries
+    # them (a kernel change needs new counters before it is committed)
+    src = os.path.join(root, "paper_2302_13529_amd", "csrc", "decrease.hip")
+    assert fields["kernel_source_sha256"] == hashlib.sha256(open(src, "rb").read()).hexdigest()
 
 
 def test_more_than_one_gpu_is_refused():
